@@ -1,0 +1,150 @@
+/*
+ * apsort -- radix sort of 32-bit integer keys on MI355X (gfx950).
+ *
+ * C ABI of libapsort.so.  The method is the radix sort of Weaver & Lynes,
+ * "Sorting Integers on the AP1000": keys are bucketed by digit (Sec. 3.2:
+ * bucket counts, cumulative totals, partial sort), digit by digit from the
+ * least significant one, each pass stable (Sec. 3.3.1), and the sorted keys
+ * are then spread evenly over P cells, cell 0 holding the smallest keys
+ * (Sec. 1.1), the cells with lower ids taking the extra key when n is not a
+ * multiple of P (footnote to Sec. 3.4.2).  On one GPU the cells are P
+ * contiguous slices of the output array; the global radix sort over all keys
+ * that Sec. 5 analyses is what runs.
+ *
+ * Conventions for every entry point
+ *   - Pointers named d_* are device pointers of the current HIP device.  Keys
+ *     are uint32_t and must be 4-byte aligned; no other alignment is assumed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream).  Work is enqueued on it and the call returns right after the
+ *     enqueue; results are ready when the stream reaches that point.
+ *   - The caller owns every d_* buffer and keeps it alive until the stream
+ *     work completes.  Input buffers are never written.
+ *   - Argument errors are detected before anything is enqueued and return
+ *     AP_ERR_INVALID (nothing is written).  A failed HIP call returns
+ *     AP_ERR_HIP, an allocation failure AP_ERR_NOMEM.  ap_last_error() gives a
+ *     thread-local message for the last failure.
+ *   - Key counts are limited to n < 2^30 per call: the single-pass scan packs a
+ *     30-bit running count with a 2-bit state in one 32-bit word.
+ */
+#ifndef APSORT_H
+#define APSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AP_OK = 0,
+    AP_ERR_INVALID = 1,    /* bad argument; nothing enqueued */
+    AP_ERR_NOMEM = 2,      /* device or host allocation failed */
+    AP_ERR_HIP = 3,        /* a HIP runtime call or launch failed */
+    AP_ERR_BUDGET = 4,     /* server: request larger than the memory budget */
+    AP_ERR_QUEUE_FULL = 5, /* server: submission queue full */
+    AP_ERR_TIMEOUT = 6,    /* server: wait timed out / ticket still pending */
+    AP_ERR_DEVICE = 7,     /* server: the request's device work failed */
+    AP_ERR_CANCELLED = 8   /* server: the server was destroyed before the request ran */
+} ap_status;
+
+#define AP_MAX_KEYS ((size_t)1 << 30) /* exclusive upper bound on n per call */
+
+/*
+ * ap_sort_u32 -- sort n keys and place them in P equal cells.
+ *
+ * Computes d_out[0..n) = the keys of d_in[0..n) in nondecreasing unsigned
+ * order (the full LSD radix sort: Sec. 3.2 bucketing per digit, Sec. 3.3.1
+ * digit order and stability).  Cell p (p = 0..P-1) is the slice
+ * [start(p), start(p+1)) with q = n / P, r = n % P, start(p) = p*q + min(p, r)
+ * (Sec. 1.1 and the footnote to Sec. 3.4.2).  When d_splitters is not NULL it
+ * receives P-1 values: d_splitters[p-1] = d_out[start(p)], the lowest key of
+ * cell p, or 0xFFFFFFFF when cell p is empty (n < P; all-ones padding in the
+ * spirit of Sec. 2.1.1).
+ *
+ *   d_in        n keys, read only.  d_in == d_out (in place) is allowed; any
+ *               other overlap of the two ranges is AP_ERR_INVALID.
+ *   d_out       n keys, written.
+ *   n           0 <= n < AP_MAX_KEYS.  n == 0 writes only the splitters.
+ *   P           number of cells, P >= 1.
+ *   d_splitters P-1 uint32_t, or NULL.
+ *
+ * Digit columns whose value is the same for every key are not sorted on (the
+ * pass is an identity); this is decided on the device, with no host sync.
+ * Scratch memory (about 4n bytes plus the scan state) comes from a per-device,
+ * per-stream cache that grows on demand; growing synchronises `stream` first.
+ * Use ap_sort_u32_ws to bring your own workspace instead.
+ */
+ap_status ap_sort_u32(const uint32_t *d_in, uint32_t *d_out, size_t n, int P,
+                      uint32_t *d_splitters, void *stream);
+
+/*
+ * ap_sort_workspace_bytes -- size of the workspace ap_sort_u32_ws needs for
+ * n keys.  Returns 0 when n >= AP_MAX_KEYS.
+ */
+size_t ap_sort_workspace_bytes(size_t n);
+
+/*
+ * ap_workspace_init -- prepare a caller-owned workspace of ws_bytes bytes
+ * (zero its control words) on `stream`.  Required once before the first
+ * ap_sort_u32_ws call on that memory; every successful sort leaves the
+ * workspace ready for the next one.
+ */
+ap_status ap_workspace_init(void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * ap_sort_u32_ws -- ap_sort_u32 with a caller-owned workspace
+ * (d_ws, ws_bytes >= ap_sort_workspace_bytes(n), 256-byte aligned, prepared
+ * once by ap_workspace_init).  Performs no allocation and no host
+ * synchronisation.  Two calls that overlap in time must not share d_ws.
+ */
+ap_status ap_sort_u32_ws(const uint32_t *d_in, uint32_t *d_out, size_t n, int P,
+                         uint32_t *d_splitters, void *d_ws, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * ap_digit_plan_u32 -- the first step of the sort on its own, for inspection:
+ * the bucket counts of every digit (Sec. 3.2, first loop of bucket()) and the
+ * pass plan derived from them.
+ *
+ *   digit_bits  digit width b, 4 <= b <= 11; D = ceil(32 / b) digits.
+ *   d_hist      D * 2^b uint32_t; d_hist[d * 2^b + v] = number of keys whose
+ *               digit d ((key >> (b*d)) & (2^b - 1)) equals v.
+ *   d_plan      D + 1 uint32_t, or NULL: d_plan[d] = 1 when pass d runs (its
+ *               digit is not constant over the keys), 0 when it is skipped;
+ *               d_plan[D] = number of passes that run.
+ */
+ap_status ap_digit_plan_u32(const uint32_t *d_in, size_t n, int digit_bits,
+                            uint32_t *d_hist, uint32_t *d_plan, void *stream);
+
+/*
+ * ap_release_cache -- free the scratch memory cached for ap_sort_u32 on the
+ * current device (all streams).  Synchronises the device first.
+ */
+ap_status ap_release_cache(void);
+
+/*
+ * Kernel timing (tracing).  While enabled on the calling thread, every launch
+ * made by a sort entry point of that thread is bracketed by two HIP events
+ * recorded on the call's stream.  ap_profile_read waits for the recorded
+ * events, adds each launch's duration to its kind, returns the totals and
+ * clears them.  Kinds: AP_KIND_HIST (bucket counts + plan), AP_KIND_PASS + d
+ * (digit pass d, d = 0..7; a pass the plan skips still records its near-empty
+ * launch), AP_KIND_FINAL (copy + splitters), AP_KIND_SEG (segmented-sort
+ * kernels).  ms and launches have at least AP_NKINDS entries.
+ */
+enum { AP_KIND_HIST = 0, AP_KIND_PASS = 1, AP_KIND_FINAL = 9, AP_KIND_SEG = 10, AP_NKINDS = 16 };
+ap_status ap_profile_enable(int on);
+ap_status ap_profile_read(double *ms, uint64_t *launches, int nkinds);
+
+/* ap_last_error -- thread-local text for the last failure of this thread. */
+const char *ap_last_error(void);
+
+/* ap_version -- library version string. */
+const char *ap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APSORT_H */

@@ -1,0 +1,174 @@
+"""ctypes binding of libapsort.so (include/apsort.h), same names as the C ABI.
+
+Argument marshalling only: every step of the sort runs in the library's HIP kernels.  Tensors are
+torch CUDA (HIP) tensors of dtype int32 or uint32 (keys are reinterpreted bit for bit as uint32);
+the stream is torch's current stream unless one is given.  PyTorch provides device memory and
+streams, nothing else.  There is no fallback: a missing library or a failed call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libapsort.so")
+
+AP_OK = 0
+STATUS = {0: "AP_OK", 1: "AP_ERR_INVALID", 2: "AP_ERR_NOMEM", 3: "AP_ERR_HIP", 4: "AP_ERR_BUDGET",
+          5: "AP_ERR_QUEUE_FULL", 6: "AP_ERR_TIMEOUT", 7: "AP_ERR_DEVICE", 8: "AP_ERR_CANCELLED"}
+MAX_KEYS = 1 << 30
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _SZ, _I, _U64P = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
+SIGNATURES = [
+    ("ap_sort_u32", _I, [_VP, _VP, _SZ, _I, _VP, _VP]),
+    ("ap_sort_workspace_bytes", _SZ, [_SZ]),
+    ("ap_workspace_init", _I, [_VP, _SZ, _VP]),
+    ("ap_sort_u32_ws", _I, [_VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
+    ("ap_digit_plan_u32", _I, [_VP, _SZ, _I, _VP, _VP, _VP]),
+    ("ap_release_cache", _I, []),
+    ("ap_profile_enable", _I, [_I]),
+    ("ap_profile_read", _I, [ctypes.POINTER(ctypes.c_double), _U64P, _I]),
+    ("ap_last_error", ctypes.c_char_p, []),
+    ("ap_version", ctypes.c_char_p, []),
+]
+
+
+class ApError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Open libapsort.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_cs_0004013_amd.build` "
+                               "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _bind_extra(L)
+        _lib = L
+    return _lib
+
+
+def _bind_extra(L):
+    """Entry points of the batched and served forms (declared when present in the library)."""
+    for name, res, args in EXTRA_SIGNATURES:
+        f = getattr(L, name, None)
+        if f is not None:
+            f.restype = res
+            f.argtypes = args
+
+
+EXTRA_SIGNATURES: list = []
+
+
+def last_error() -> str:
+    return lib().ap_last_error().decode(errors="replace")
+
+
+def check(status: int, where: str) -> None:
+    if status != AP_OK:
+        raise ApError(status, where, last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _keys_ptr(t, name: str) -> int:
+    torch = _torch()
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise TypeError(f"{name}: int32/uint32 tensor expected, got {t.dtype}")
+    if not t.is_cuda:
+        raise TypeError(f"{name}: device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def ap_sort_u32(t_in, t_out, P: int = 64, t_splitters=None, stream=None) -> None:
+    """Sort t_in into t_out (may be the same tensor) and write the P-1 splitters (A1-A7)."""
+    n = t_in.numel()
+    if t_out.numel() != n:
+        raise ValueError("input and output sizes differ")
+    spl = 0
+    if t_splitters is not None:
+        if t_splitters.numel() < max(P - 1, 0):
+            raise ValueError("splitter tensor needs P-1 entries")
+        spl = _keys_ptr(t_splitters, "splitters")
+    st = lib().ap_sort_u32(_keys_ptr(t_in, "in") if n else None, _keys_ptr(t_out, "out") if n else None, n, P,
+                           spl or None, _stream(stream))
+    check(st, "ap_sort_u32")
+
+
+def ap_sort_workspace_bytes(n: int) -> int:
+    return int(lib().ap_sort_workspace_bytes(n))
+
+
+def ap_workspace_init(t_ws, stream=None) -> None:
+    check(lib().ap_workspace_init(t_ws.data_ptr(), t_ws.numel() * t_ws.element_size(), _stream(stream)),
+          "ap_workspace_init")
+
+
+def ap_sort_u32_ws(t_in, t_out, P: int, t_splitters, t_ws, stream=None) -> None:
+    n = t_in.numel()
+    spl = _keys_ptr(t_splitters, "splitters") if t_splitters is not None else None
+    st = lib().ap_sort_u32_ws(_keys_ptr(t_in, "in") if n else None, _keys_ptr(t_out, "out") if n else None, n, P,
+                              spl, t_ws.data_ptr(), t_ws.numel() * t_ws.element_size(), _stream(stream))
+    check(st, "ap_sort_u32_ws")
+
+
+def ap_digit_plan_u32(t_in, digit_bits: int, t_hist, t_plan=None, stream=None) -> None:
+    """Per-digit bucket counts (D x 2^bits) and the pass plan (D run flags + pass count)."""
+    n = t_in.numel()
+    D = (32 + digit_bits - 1) // digit_bits
+    if t_hist.numel() < D << digit_bits:
+        raise ValueError("histogram tensor too small")
+    if t_plan is not None and t_plan.numel() < D + 1:
+        raise ValueError("plan tensor needs D+1 entries")
+    st = lib().ap_digit_plan_u32(_keys_ptr(t_in, "in") if n else None, n, digit_bits, _keys_ptr(t_hist, "hist"),
+                                 _keys_ptr(t_plan, "plan") if t_plan is not None else None, _stream(stream))
+    check(st, "ap_digit_plan_u32")
+
+
+AP_KIND_HIST, AP_KIND_PASS, AP_KIND_FINAL, AP_KIND_SEG, AP_NKINDS = 0, 1, 9, 10, 16
+
+
+def ap_profile_enable(on: bool = True) -> None:
+    check(lib().ap_profile_enable(1 if on else 0), "ap_profile_enable")
+
+
+def ap_profile_read() -> tuple[list[float], list[int]]:
+    """(milliseconds, launches) per kernel kind since the last read; waits for the events."""
+    ms = (ctypes.c_double * AP_NKINDS)()
+    cnt = (ctypes.c_uint64 * AP_NKINDS)()
+    check(lib().ap_profile_read(ms, cnt, AP_NKINDS), "ap_profile_read")
+    return list(ms), list(cnt)
+
+
+def ap_release_cache() -> None:
+    check(lib().ap_release_cache(), "ap_release_cache")
+
+
+def ap_version() -> str:
+    return lib().ap_version().decode()

@@ -1,0 +1,382 @@
+// Host side of libapsort.so: argument checks, workspace layout and cache, launch sequence, and the
+// C entry points declared in include/apsort.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "apsort.h"
+#include "apsort_kernels.h"
+#include "apsort_internal.h"
+
+namespace aps {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string t_err;
+
+ap_status fail(ap_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return st;
+}
+
+ap_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? AP_ERR_NOMEM : AP_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool debug_sync() {
+  static const bool on = [] {
+    const char* s = std::getenv("AP_DEBUG_SYNC");
+    return s && s[0] && s[0] != '0';
+  }();
+  return on;
+}
+
+ap_status check_launch(hipStream_t s, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  if (debug_sync()) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, what);
+  }
+  return AP_OK;
+}
+
+int device_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  static std::mutex mu;
+  static std::vector<int> cus;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cus.size() <= dev) cus.resize(dev + 1, 0);
+  if (!cus[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
+// ---------------------------------------------------------------- configuration
+// Digit width and tile shape of the single-array sort.  8-bit digits (4 passes for 32-bit keys);
+// large arrays use 8192-key tiles (4 waves x 32 keys per lane), small ones 2048-key tiles so that
+// the grid still covers every compute unit.
+constexpr int kBits = 8;
+constexpr int kRadix = 1 << kBits;
+constexpr int kDigits = (32 + kBits - 1) / kBits;
+constexpr int kHistThreads = 512;
+constexpr int kWaves = 4;
+constexpr int kIptLarge = 32;
+constexpr int kIptSmall = 8;
+constexpr uint32_t kSmallN = 1u << 22;
+
+static int tile_keys_for(size_t n) { return (n >= kSmallN ? kIptLarge : kIptSmall) * kWaves * 64; }
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace layout (bytes from the 256-byte aligned base):
+//   [hist D*R u32][base D*R u32][plan 32 u32][done 1 u32 | pad][tile counters 8 u32 | pad]
+//   [status D * ntiles * R u32][tmp n u32]
+// hist and done are self-clearing; tile counters and status are cleared by k_hist_plan.
+Layout layout_for(size_t n) {
+  Layout L{};
+  const int T = tile_keys_for(n);
+  L.tile_keys = T;
+  L.ntiles = (uint32_t)((n + T - 1) / T);
+  size_t off = 0;
+  L.hist = off;   off += align_up(sizeof(uint32_t) * kDigits * kRadix, 256);
+  L.base = off;   off += align_up(sizeof(uint32_t) * kDigits * kRadix, 256);
+  L.plan = off;   off += align_up(sizeof(uint32_t) * PL_WORDS, 256);
+  L.done = off;   off += 256;
+  L.tctr = off;   off += 256;
+  L.status = off; off += align_up(sizeof(uint32_t) * (size_t)kDigits * L.ntiles * kRadix, 256);
+  L.zero_bytes = off - L.tctr;  // tile counters + status, cleared every call
+  L.tmp = off;    off += align_up(sizeof(uint32_t) * n, 256);
+  L.total = off;
+  L.init_bytes = L.tctr;        // hist, base, plan, done: zeroed once at workspace creation
+  return L;
+}
+
+// ---------------------------------------------------------------- launch sequence
+ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl,
+                       void* ws, const Layout& L, hipStream_t s) {
+  char* w = static_cast<char*>(ws);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
+  uint32_t* base = reinterpret_cast<uint32_t*>(w + L.base);
+  uint32_t* plan = reinterpret_cast<uint32_t*>(w + L.plan);
+  uint32_t* done = reinterpret_cast<uint32_t*>(w + L.done);
+  uint32_t* tctr = reinterpret_cast<uint32_t*>(w + L.tctr);
+  uint32_t* status = reinterpret_cast<uint32_t*>(w + L.status);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(w + L.tmp);
+  const uint32_t nn = (uint32_t)n;
+  const int cus = device_cus();
+  const int inplace = (d_in == d_out) ? 1 : 0;
+
+  // A1 + A2
+  {
+    uint32_t g = (uint32_t)std::min<size_t>((n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16),
+                                            (size_t)2 * cus);
+    g = std::max<uint32_t>(g, 1);
+    prof_begin(AP_KIND_HIST, s);
+    hipLaunchKernelGGL((k_hist_plan<kBits, kHistThreads>), dim3(g), dim3(kHistThreads), 0, s, d_in, nn,
+                       hist, base, plan, done, reinterpret_cast<uint4*>(tctr), (uint32_t)(L.zero_bytes / 16),
+                       inplace, (uint32_t*)nullptr);
+    prof_end(s);
+    ap_status st = check_launch(s, "k_hist_plan");
+    if (st != AP_OK) return st;
+  }
+  // A3-A6: one launch per digit; passes the plan skips exit at once
+  for (int d = 0; d < kDigits; ++d) {
+    uint32_t* st_d = status + (size_t)d * L.ntiles * kRadix;
+    prof_begin(AP_KIND_PASS + d, s);
+    if (L.tile_keys == kIptLarge * kWaves * 64)
+      hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptLarge>), dim3(L.ntiles), dim3(kWaves * 64), 0, s, d_in,
+                         d_out, tmp, nn, d, plan, base + d * kRadix, st_d, tctr);
+    else
+      hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptSmall>), dim3(L.ntiles), dim3(kWaves * 64), 0, s, d_in,
+                         d_out, tmp, nn, d, plan, base + d * kRadix, st_d, tctr);
+    prof_end(s);
+    ap_status st = check_launch(s, "k_pass");
+    if (st != AP_OK) return st;
+  }
+  // A7
+  {
+    const size_t work = std::max<size_t>(n / 4, (size_t)P);
+    uint32_t g = (uint32_t)std::min<size_t>((work + 255 * 8) / (256 * 8), (size_t)4 * cus);
+    g = std::max<uint32_t>(g, 1);
+    prof_begin(AP_KIND_FINAL, s);
+    hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, d_in, d_out, tmp, nn, plan, (uint32_t)P,
+                       P > 1 ? d_spl : nullptr);
+    prof_end(s);
+    ap_status st = check_launch(s, "k_finalize");
+    if (st != AP_OK) return st;
+  }
+  return AP_OK;
+}
+
+ap_status fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s) {
+  if (!count) return AP_OK;
+  uint32_t g = (uint32_t)std::min<size_t>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, s, p, value, count);
+  return check_launch(s, "k_fill_u32");
+}
+
+// Inspection entry point: k_hist_plan alone with a given digit width, on a small per-device
+// control block (hist up to 6144 counters, base, plan, done) that stays zero between calls.
+template <int BITS>
+static ap_status launch_plan_only(const uint32_t* d_in, uint32_t n, uint32_t* ctl, uint32_t* d_hist,
+                                  uint32_t* d_plan, hipStream_t s) {
+  constexpr int R = 1 << BITS, D = (32 + BITS - 1) / BITS;
+  uint32_t* hist = ctl;
+  uint32_t* base = ctl + 8192;
+  uint32_t* plan = ctl + 16384;
+  uint32_t* done = ctl + 16384 + PL_WORDS;
+  const int cus = device_cus();
+  uint32_t g = (uint32_t)std::min<size_t>(((size_t)n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16),
+                                          (size_t)2 * cus);
+  g = std::max<uint32_t>(g, 1);
+  hipLaunchKernelGGL((k_hist_plan<BITS, kHistThreads>), dim3(g), dim3(kHistThreads), 0, s, d_in, n, hist, base,
+                     plan, done, (uint4*)nullptr, 0u, 0, d_hist);
+  ap_status st = check_launch(s, "k_hist_plan");
+  if (st != AP_OK || !d_plan) return st;
+  // d_plan[d] = run flag of pass d, d_plan[D] = number of passes
+  hipError_t e = hipMemcpyAsync(d_plan, plan + PL_RUN, sizeof(uint32_t) * D, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_plan + D, plan + PL_NPASS, sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+  (void)R;
+  return e == hipSuccess ? AP_OK : hip_fail(e, "hipMemcpyAsync(plan)");
+}
+
+ap_status enqueue_digit_plan(const uint32_t* d_in, size_t n, int bits, uint32_t* d_hist, uint32_t* d_plan,
+                             hipStream_t s) {
+  static std::mutex mu;
+  static std::vector<uint32_t*> ctl_per_dev;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  uint32_t* ctl = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)ctl_per_dev.size() <= dev) ctl_per_dev.resize(dev + 1, nullptr);
+    if (!ctl_per_dev[dev]) {
+      uint32_t* p = nullptr;
+      e = hipMalloc(&p, sizeof(uint32_t) * (16384 + 256));
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan control block)");
+      ap_status st = fill_u32(p, 0u, 16384 + 256, s);
+      if (st != AP_OK) return st;
+      ctl_per_dev[dev] = p;
+    }
+    ctl = ctl_per_dev[dev];
+  }
+  const int D = (32 + bits - 1) / bits;
+  if (n == 0) {
+    ap_status st = fill_u32(d_hist, 0u, (size_t)D << bits, s);
+    if (st == AP_OK && d_plan) st = fill_u32(d_plan, 0u, (size_t)D + 1, s);
+    return st;
+  }
+  const uint32_t nn = (uint32_t)n;
+  switch (bits) {
+    case 4: return launch_plan_only<4>(d_in, nn, ctl, d_hist, d_plan, s);
+    case 5: return launch_plan_only<5>(d_in, nn, ctl, d_hist, d_plan, s);
+    case 6: return launch_plan_only<6>(d_in, nn, ctl, d_hist, d_plan, s);
+    case 7: return launch_plan_only<7>(d_in, nn, ctl, d_hist, d_plan, s);
+    case 8: return launch_plan_only<8>(d_in, nn, ctl, d_hist, d_plan, s);
+    case 9: return launch_plan_only<9>(d_in, nn, ctl, d_hist, d_plan, s);
+    case 10: return launch_plan_only<10>(d_in, nn, ctl, d_hist, d_plan, s);
+    case 11: return launch_plan_only<11>(d_in, nn, ctl, d_hist, d_plan, s);
+    default: return fail(AP_ERR_INVALID, "digit_bits must be in [4, 11]");
+  }
+}
+
+ap_status check_sort_args(const uint32_t* d_in, const uint32_t* d_out, size_t n, int P) {
+  if (P < 1) return fail(AP_ERR_INVALID, "P must be >= 1 (got %d)", P);
+  if (n >= AP_MAX_KEYS) return fail(AP_ERR_INVALID, "n must be < 2^30 (got %zu)", n);
+  if (n == 0) return AP_OK;
+  if (!d_in || !d_out) return fail(AP_ERR_INVALID, "NULL key buffer with n > 0");
+  if (((uintptr_t)d_in | (uintptr_t)d_out) & 3u) return fail(AP_ERR_INVALID, "key buffers must be 4-byte aligned");
+  if (d_in != d_out) {
+    const uintptr_t a0 = (uintptr_t)d_in, a1 = a0 + n * 4, b0 = (uintptr_t)d_out, b1 = b0 + n * 4;
+    if (a0 < b1 && b0 < a1) return fail(AP_ERR_INVALID, "input and output overlap without being equal");
+  }
+  return AP_OK;
+}
+
+ap_status sort_with_ws(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
+                       size_t ws_bytes, hipStream_t s) {
+  if (n == 0) return P > 1 && d_spl ? fill_u32(d_spl, 0xFFFFFFFFu, (size_t)P - 1, s) : AP_OK;
+  const Layout L = layout_for(n);
+  if (!ws || ws_bytes < L.total) return fail(AP_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, L.total);
+  if ((uintptr_t)ws & 255u) return fail(AP_ERR_INVALID, "workspace must be 256-byte aligned");
+  return enqueue_sort(d_in, d_out, n, P, d_spl, ws, L, s);
+}
+
+// ---------------------------------------------------------------- workspace cache
+struct CacheEntry {
+  int dev;
+  hipStream_t stream;
+  void* ptr;
+  size_t bytes;
+};
+static std::mutex g_cache_mu;
+static std::vector<CacheEntry> g_cache;
+
+ap_status cached_workspace(size_t need, hipStream_t s, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& c : g_cache) {
+    if (c.dev == dev && c.stream == s) {
+      if (c.bytes >= need) {
+        *out = c.ptr;
+        return AP_OK;
+      }
+      e = hipStreamSynchronize(s);  // the old block may still be in use on this stream
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      (void)hipFree(c.ptr);
+      c.ptr = nullptr;
+      c.bytes = 0;
+      const size_t bytes = std::max(need, c.bytes + c.bytes / 4);
+      e = hipMalloc(&c.ptr, bytes);
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+      c.bytes = bytes;
+      ap_status st = fill_u32(static_cast<uint32_t*>(c.ptr), 0u, layout_for(0).init_bytes / 4, s);
+      if (st != AP_OK) return st;
+      *out = c.ptr;
+      return AP_OK;
+    }
+  }
+  CacheEntry c{dev, s, nullptr, need};
+  e = hipMalloc(&c.ptr, need);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+  ap_status st = fill_u32(static_cast<uint32_t*>(c.ptr), 0u, layout_for(0).init_bytes / 4, s);
+  if (st != AP_OK) {
+    (void)hipFree(c.ptr);
+    return st;
+  }
+  g_cache.push_back(c);
+  *out = c.ptr;
+  return AP_OK;
+}
+
+ap_status release_cache() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  std::vector<CacheEntry> keep;
+  for (auto& c : g_cache) {
+    if (c.dev == dev) (void)hipFree(c.ptr);
+    else keep.push_back(c);
+  }
+  g_cache.swap(keep);
+  return AP_OK;
+}
+
+}  // namespace aps
+
+// ================================================================ C ABI
+using namespace aps;
+
+extern "C" {
+
+const char* ap_last_error(void) { return t_err.c_str(); }
+
+const char* ap_version(void) { return "apsort 0.1 gfx950"; }
+
+size_t ap_sort_workspace_bytes(size_t n) {
+  if (n >= AP_MAX_KEYS) return 0;
+  return layout_for(n).total;
+}
+
+ap_status ap_workspace_init(void* d_ws, size_t ws_bytes, void* stream) {
+  const size_t need = layout_for(0).init_bytes;
+  if (!d_ws || ws_bytes < need) return fail(AP_ERR_INVALID, "workspace too small for its control block");
+  if ((uintptr_t)d_ws & 255u) return fail(AP_ERR_INVALID, "workspace must be 256-byte aligned");
+  return fill_u32(static_cast<uint32_t*>(d_ws), 0u, need / 4, static_cast<hipStream_t>(stream));
+}
+
+ap_status ap_sort_u32(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_splitters,
+                      void* stream) {
+  ap_status st = check_sort_args(d_in, d_out, n, P);
+  if (st != AP_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) return sort_with_ws(d_in, d_out, 0, P, d_splitters, nullptr, 0, s);
+  const Layout L = layout_for(n);
+  void* ws = nullptr;
+  st = cached_workspace(L.total, s, &ws);
+  if (st != AP_OK) return st;
+  return enqueue_sort(d_in, d_out, n, P, d_splitters, ws, L, s);
+}
+
+ap_status ap_sort_u32_ws(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_splitters,
+                         void* d_ws, size_t ws_bytes, void* stream) {
+  ap_status st = check_sort_args(d_in, d_out, n, P);
+  if (st != AP_OK) return st;
+  return sort_with_ws(d_in, d_out, n, P, d_splitters, d_ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+ap_status ap_digit_plan_u32(const uint32_t* d_in, size_t n, int digit_bits, uint32_t* d_hist, uint32_t* d_plan,
+                            void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (digit_bits < 4 || digit_bits > 11) return fail(AP_ERR_INVALID, "digit_bits must be in [4, 11]");
+  if (n >= AP_MAX_KEYS) return fail(AP_ERR_INVALID, "n must be < 2^30");
+  if (!d_hist) return fail(AP_ERR_INVALID, "d_hist is NULL");
+  if (n && (!d_in || ((uintptr_t)d_in & 3u))) return fail(AP_ERR_INVALID, "bad key pointer");
+  return enqueue_digit_plan(d_in, n, digit_bits, d_hist, d_plan, s);
+}
+
+ap_status ap_release_cache(void) { return release_cache(); }
+
+}  // extern "C"

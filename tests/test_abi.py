@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point declared in include/*.h (CPU only: no
+compute calls; argument errors are rejected on the host before anything touches a device)."""
+from __future__ import annotations
+
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_cs_0004013_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DECL = re.compile(r"^\s*(?:const\s+char\s*\*|ap_status|size_t|void)\s*\**\s*(ap_\w+)\s*\(", re.M)
+
+
+def declared() -> list[str]:
+    names = []
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        names += DECL.findall(open(h).read())
+    return sorted(set(names))
+
+
+def exported() -> set[str]:
+    out = subprocess.run(["nm", "-D", "--defined-only", binding.LIB_PATH], check=True,
+                         stdout=subprocess.PIPE, text=True).stdout
+    return {line.split()[-1] for line in out.splitlines() if line.strip()}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    from paper_cs_0004013_amd import build
+    if build.is_stale():
+        build.build()
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for must in ("ap_sort_u32", "ap_sort_u32_ws", "ap_sort_workspace_bytes", "ap_digit_plan_u32",
+                 "ap_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported():
+    missing = [n for n in declared() if n not in exported()]
+    assert not missing, missing
+
+
+def test_library_loads_and_binds():
+    L = binding.lib()
+    for n in declared():
+        assert hasattr(L, n)
+    assert "gfx950" in binding.ap_version()
+
+
+def test_workspace_size_is_host_only():
+    L = binding.lib()
+    assert L.ap_sort_workspace_bytes(1 << 30) == 0
+    a, b = L.ap_sort_workspace_bytes(1 << 20), L.ap_sort_workspace_bytes(1 << 26)
+    assert (1 << 22) < a < b and b >= 4 * (1 << 26)
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = binding.lib()
+    assert L.ap_sort_u32(None, None, 10, 64, None, None) == 1        # NULL buffers
+    assert "NULL" in binding.last_error()
+    assert L.ap_sort_u32(16, 32, 10, 0, None, None) == 1               # P < 1
+    assert L.ap_sort_u32(16, 32, 1 << 30, 64, None, None) == 1         # n too large
+    assert L.ap_sort_u32(18, 1024, 10, 64, None, None) == 1            # misaligned
+    assert L.ap_sort_u32(4096, 4100, 10, 64, None, None) == 1          # partial overlap
+    assert L.ap_digit_plan_u32(4096, 10, 3, 8192, None, None) == 1     # digit width
+    assert L.ap_sort_u32_ws(4096, 8192, 1000, 4, None, 65536, 16, None) == 1  # workspace too small

@@ -1,0 +1,190 @@
+"""Parity of the single-array sort (A1-A7) with the CPU oracle, through the C ABI.
+
+Every result is compared element by element with the oracle (bit-exact: integer work), and the
+splitters with the oracle's; the invariant checks of tests/invariants.py run as well.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0004013_amd import inputs
+from tests import invariants as inv
+from tests.gpu_util import announce, gpu_sort, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(keys: np.ndarray, P: int = 64, **kw):
+    announce(f"sort n={keys.size} P={P} {kw}")
+    out, spl = gpu_sort(keys, P, **kw)
+    want = oracle.sort_u32(keys)
+    assert out.size == want.size
+    bad = np.flatnonzero(out != want)
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+    assert np.array_equal(spl, oracle.splitters(want, P))
+    return out, spl
+
+
+def test_uniform_2pow20_config():
+    """2^20 i.i.d. uniform keys in [0, 2^31-1], seed 0, P = 64."""
+    ks = inputs.keyset("a", 1 << 20, seed=0)
+    out, spl = _check(ks.keys)
+    assert inv.is_nondecreasing(out) and inv.same_multiset(out, ks.keys)
+    inv.check_splitters(out, 64, spl)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 63, 64, 65, 255, 256, 257, 2047, 2048, 2049, 8191, 8192,
+                               8193, 100_000, (1 << 20) + 7, (1 << 22) - 1, 1 << 22, (1 << 22) + 1,
+                               3 * 8192 * 7 + 5])
+def test_sizes_full_range(n):
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)  # bit 31 set too
+    _check(keys)
+
+
+@pytest.mark.parametrize("dist", inputs.DISTS)
+def test_distributions_2pow22(dist):
+    _check(inputs.keyset(dist, (1 << 22) + 13, seed=11).keys)
+
+
+@pytest.mark.parametrize("seed,dist", list(zip(range(1, 6), inputs.DISTS)))
+def test_distributions_full_size(seed, dist):
+    """2^26 keys, distributions (a)-(e) with seeds 1-5 (the benchmark's workloads)."""
+    _check(inputs.keyset(dist, 1 << 26, seed=seed).keys)
+
+
+def test_adversarial_full_size():
+    """2^27 keys: top 16 bits take 4 values, hot keys duplicated 1000x."""
+    _check(inputs.adversarial(1 << 27, seed=0).keys)
+
+
+@pytest.mark.parametrize("n", [0, 1, 5, 64, 1000, 8193, 1 << 20])
+@pytest.mark.parametrize("P", [1, 2, 3, 63, 64, 65])
+def test_cells_and_splitters(n, P):
+    rng = np.random.default_rng(n + P)
+    keys = rng.integers(0, 1 << 31, size=n, dtype=np.uint64).astype(np.uint32)
+    _check(keys, P)
+    if n:
+        _check(keys, n + 1)       # more cells than keys: empty cells get all-ones splitters
+
+
+@pytest.mark.parametrize("n", [1000, 65_537, (1 << 22) + 3])
+def test_in_place(n):
+    rng = np.random.default_rng(5)
+    keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    _check(keys, inplace=True)
+    _check(keys >> np.uint32(8), inplace=True)   # 3 passes run: odd count in place needs a copy
+    _check(np.full(n, 77, np.uint32), inplace=True)
+
+
+@pytest.mark.parametrize("pad", [1, 2, 3])
+def test_unaligned_start(pad):
+    keys = inputs.keyset("d", (1 << 20) + 3, seed=pad).keys
+    _check(keys, pad_front=pad)
+
+
+def test_closed_forms():
+    rng = np.random.default_rng(0)
+    n = (1 << 20) + 123
+    perm = rng.permutation(n).astype(np.uint32)
+    out, spl = _check(perm)
+    assert np.array_equal(out, np.arange(n, dtype=np.uint32))
+    asc = np.sort(rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32))
+    _check(asc)
+    _check(asc[::-1].copy())
+
+
+def _plan(keys: np.ndarray, bits: int):
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    D = (32 + bits - 1) // bits
+    t_in, _ = to_dev(keys)
+    h = torch.zeros(D << bits, dtype=torch.int32, device="cuda")
+    p = torch.zeros(D + 1, dtype=torch.int32, device="cuda")
+    binding.ap_digit_plan_u32(t_in, bits, h, p)
+    torch.cuda.synchronize()
+    return to_host(h).reshape(D, 1 << bits), to_host(p)
+
+
+@pytest.mark.parametrize("bits", [4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("dist", ["a", "c", "e"])
+def test_digit_histograms_and_plan(bits, dist):
+    """A1/A2: bucket counts of every digit equal the oracle's; a pass runs iff its digit column
+    is not constant."""
+    keys = inputs.keyset(dist, 300_001, seed=bits).keys
+    announce(f"digit plan bits={bits} dist={dist}")
+    h, plan = _plan(keys, bits)
+    D = h.shape[0]
+    run = []
+    for d in range(D):
+        want = oracle.digit_hist(keys, d * bits, min(bits, 32 - d * bits))
+        got = h[d, :want.size].astype(np.uint64)
+        assert np.array_equal(got, want), f"digit {d}"
+        assert not h[d, want.size:].any()
+        run.append(0 if want.max() == keys.size else 1)
+    assert plan[:D].tolist() == run
+    assert plan[D] == sum(run)
+
+
+def test_pass_skip_counts():
+    keys24 = inputs.keyset("a", 100_000, 3).keys >> np.uint32(7)      # < 2^24: 3 passes
+    assert _plan(keys24, 8)[1][4] == 3
+    assert _plan(np.full(1000, 9, np.uint32), 8)[1][4] == 0            # constant: 0 passes
+    adv = inputs.adversarial(1 << 20, 0).keys                           # 4 top values: 4 passes
+    assert _plan(adv, 8)[1][4] == 4
+
+
+def test_repeatable_bitwise():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    for keys in (inputs.keyset("a", (1 << 22) + 5, 1).keys, inputs.keyset("e", 1 << 22, 2).keys):
+        announce(f"repeat n={keys.size}")
+        t_in, _ = to_dev(keys)
+        t_out = torch.empty_like(t_in)
+        first = None
+        for _ in range(20):
+            binding.ap_sort_u32(t_in, t_out, 64, None)
+            cur = t_out.clone()
+            if first is None:
+                first = cur
+            else:
+                assert torch.equal(cur, first)
+        assert np.array_equal(to_host(first), oracle.sort_u32(keys))
+
+
+def test_caller_workspace():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    n = (1 << 21) + 9
+    keys = inputs.keyset("d", n, 4).keys
+    ws = torch.empty(binding.ap_sort_workspace_bytes(n) + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + binding.ap_sort_workspace_bytes(n)]
+    binding.ap_workspace_init(ws)
+    t_in, _ = to_dev(keys)
+    t_out = torch.empty_like(t_in)
+    spl = torch.empty(63, dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        binding.ap_sort_u32_ws(t_in, t_out, 64, spl, ws)
+    torch.cuda.synchronize()
+    want = oracle.sort_u32(keys)
+    assert np.array_equal(to_host(t_out), want)
+    assert np.array_equal(to_host(spl), oracle.splitters(want, 64))
+    small = keys[:1000].copy()                         # smaller call on the same workspace
+    t2, _ = to_dev(small)
+    o2 = torch.empty_like(t2)
+    binding.ap_sort_u32_ws(t2, o2, 64, spl, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(o2), oracle.sort_u32(small))
+
+
+def test_invalid_args_raise():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    base = torch.zeros(101, dtype=torch.int32, device="cuda")
+    with pytest.raises(binding.ApError):
+        binding.ap_sort_u32(base[0:100], base[1:101], 64)      # partial overlap
+    with pytest.raises(binding.ApError):
+        binding.ap_sort_u32(base[0:100], base[0:100], 0)       # P < 1
