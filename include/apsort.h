@@ -137,6 +137,23 @@ enum { AP_KIND_HIST = 0, AP_KIND_PASS = 1, AP_KIND_FINAL = 9, AP_KIND_SEG = 10, 
 ap_status ap_profile_enable(int on);
 ap_status ap_profile_read(double *ms, uint64_t *launches, int nkinds);
 
+/*
+ * Rank primitive of the digit pass.  The default rank gives each key the
+ * value returned by an LDS atomic add on a per-wave bucket counter, which is
+ * stable because the LDS services the conflicting lanes of one instruction in
+ * lane order; a device self-check (run once per device by the first
+ * ap_sort_u32, ap_workspace_init or ap_server_create) confirms that property
+ * before it is relied on.  The alternative rank builds per-bucket lane masks
+ * in LDS and needs no ordering property.
+ *
+ * ap_rank_check_state: -1 = device not checked yet, 0 = check failed (the
+ * mask rank is used), 1 = check passed (the atomic rank is used).
+ * ap_set_rank_mode: 0 = automatic (default), 1 = always the mask rank
+ * (process-wide; for testing both paths).
+ */
+int ap_rank_check_state(void);
+ap_status ap_set_rank_mode(int mode);
+
 /* ap_last_error -- thread-local text for the last failure of this thread. */
 const char *ap_last_error(void);
 

@@ -29,6 +29,8 @@ SIGNATURES = [
     ("ap_release_cache", _I, []),
     ("ap_profile_enable", _I, [_I]),
     ("ap_profile_read", _I, [ctypes.POINTER(ctypes.c_double), _U64P, _I]),
+    ("ap_rank_check_state", _I, []),
+    ("ap_set_rank_mode", _I, [_I]),
     ("ap_last_error", ctypes.c_char_p, []),
     ("ap_version", ctypes.c_char_p, []),
 ]
@@ -164,6 +166,15 @@ def ap_profile_read() -> tuple[list[float], list[int]]:
     cnt = (ctypes.c_uint64 * AP_NKINDS)()
     check(lib().ap_profile_read(ms, cnt, AP_NKINDS), "ap_profile_read")
     return list(ms), list(cnt)
+
+
+def ap_rank_check_state() -> int:
+    return int(lib().ap_rank_check_state())
+
+
+def ap_set_rank_mode(mode: int) -> None:
+    """0 = automatic (atomic rank when the device passed its lane-order check), 1 = mask rank."""
+    check(lib().ap_set_rank_mode(mode), "ap_set_rank_mode")
 
 
 def ap_release_cache() -> None:

@@ -67,6 +67,59 @@ int device_cus() {
   return cus[dev];
 }
 
+// ---------------------------------------------------------------- lane-order check
+// The atomic rank of k_pass needs the LDS to service the conflicting lanes of one atomic
+// instruction in lane order.  k_lane_order_probe checks that once per device; until a device has
+// passed the check, or if it fails, the passes use the order-agnostic match rank.
+static std::mutex g_lane_mu;
+static std::vector<int> g_lane_state;  // per device: -1 unknown, 0 failed, 1 passed
+
+static int g_force_match = 0;  // testing hook: 1 = always use the match rank
+
+bool lane_order_ok() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  return !g_force_match && dev < (int)g_lane_state.size() && g_lane_state[dev] == 1;
+}
+
+int lane_order_state() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  return dev < (int)g_lane_state.size() ? g_lane_state[dev] : -1;
+}
+
+void set_rank_mode(int mode) {
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  g_force_match = mode == 1 ? 1 : 0;
+}
+
+ap_status check_lane_order(hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> lk(g_lane_mu);
+    if ((int)g_lane_state.size() <= dev) g_lane_state.resize(dev + 1, -1);
+    if (g_lane_state[dev] != -1) return AP_OK;
+  }
+  uint32_t* d_flag = nullptr;
+  e = hipMalloc(&d_flag, 256);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(lane-order flag)");
+  uint32_t h_flag = 1u;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_flag, 0u, (size_t)1);
+  hipLaunchKernelGGL(k_lane_order_probe, dim3(64), dim3(256), 0, s, d_flag, 180u);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&h_flag, d_flag, sizeof h_flag, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_flag);
+  if (e != hipSuccess) return hip_fail(e, "lane-order check");
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  g_lane_state[dev] = (h_flag == 0u) ? 1 : 0;
+  return AP_OK;
+}
+
 // ---------------------------------------------------------------- configuration
 // Digit width and tile shape of the single-array sort.  8-bit digits (4 passes for 32-bit keys);
 // large arrays use 8192-key tiles (4 waves x 32 keys per lane), small ones 2048-key tiles so that
@@ -75,17 +128,26 @@ constexpr int kBits = 8;
 constexpr int kRadix = 1 << kBits;
 constexpr int kDigits = (32 + kBits - 1) / kBits;
 constexpr int kHistThreads = 512;
+constexpr uint32_t kHistCopies = 32;  // copies of the global counters (contention / 32)
 constexpr int kWaves = 4;
 constexpr int kIptLarge = 32;
 constexpr int kIptSmall = 8;
 constexpr uint32_t kSmallN = 1u << 22;
+
+// LDS copies of the counters in k_hist_plan: as many as fit in 64 KiB, at most 16.
+template <int BITS>
+constexpr int hist_lcopies() {
+  constexpr int hw = ((32 + BITS - 1) / BITS) << BITS;
+  constexpr int c = 16384 / (hw + 1);
+  return c < 1 ? 1 : (c > 16 ? 16 : c);
+}
 
 static int tile_keys_for(size_t n) { return (n >= kSmallN ? kIptLarge : kIptSmall) * kWaves * 64; }
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace layout (bytes from the 256-byte aligned base):
-//   [hist D*R u32][base D*R u32][plan 32 u32][done 1 u32 | pad][tile counters 8 u32 | pad]
+//   [hist copies*D*R u32][base D*R u32][plan 32 u32][done 1 u32 | pad][tile counters 8 u32 | pad]
 //   [status D * ntiles * R u32][tmp n u32]
 // hist and done are self-clearing; tile counters and status are cleared by k_hist_plan.
 Layout layout_for(size_t n) {
@@ -94,7 +156,7 @@ Layout layout_for(size_t n) {
   L.tile_keys = T;
   L.ntiles = (uint32_t)((n + T - 1) / T);
   size_t off = 0;
-  L.hist = off;   off += align_up(sizeof(uint32_t) * kDigits * kRadix, 256);
+  L.hist = off;   off += align_up(sizeof(uint32_t) * kHistCopies * kDigits * kRadix, 256);
   L.base = off;   off += align_up(sizeof(uint32_t) * kDigits * kRadix, 256);
   L.plan = off;   off += align_up(sizeof(uint32_t) * PL_WORDS, 256);
   L.done = off;   off += 256;
@@ -128,23 +190,36 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
                                             (size_t)2 * cus);
     g = std::max<uint32_t>(g, 1);
     prof_begin(AP_KIND_HIST, s);
-    hipLaunchKernelGGL((k_hist_plan<kBits, kHistThreads>), dim3(g), dim3(kHistThreads), 0, s, d_in, nn,
+    hipLaunchKernelGGL((k_hist_plan<kBits, kHistThreads, hist_lcopies<kBits>()>), dim3(g), dim3(kHistThreads), 0, s,
+                       d_in, nn,
                        hist, base, plan, done, reinterpret_cast<uint4*>(tctr), (uint32_t)(L.zero_bytes / 16),
-                       inplace, (uint32_t*)nullptr);
+                       inplace, (uint32_t*)nullptr, kHistCopies);
     prof_end(s);
     ap_status st = check_launch(s, "k_hist_plan");
     if (st != AP_OK) return st;
   }
   // A3-A6: one launch per digit; passes the plan skips exit at once
+  const bool atomic_rank = lane_order_ok();
   for (int d = 0; d < kDigits; ++d) {
     uint32_t* st_d = status + (size_t)d * L.ntiles * kRadix;
+    const uint32_t* base_d = base + d * kRadix;
     prof_begin(AP_KIND_PASS + d, s);
-    if (L.tile_keys == kIptLarge * kWaves * 64)
-      hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptLarge>), dim3(L.ntiles), dim3(kWaves * 64), 0, s, d_in,
-                         d_out, tmp, nn, d, plan, base + d * kRadix, st_d, tctr);
-    else
-      hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptSmall>), dim3(L.ntiles), dim3(kWaves * 64), 0, s, d_in,
-                         d_out, tmp, nn, d, plan, base + d * kRadix, st_d, tctr);
+    const dim3 grid(L.ntiles), block(kWaves * 64);
+    if (L.tile_keys == kIptLarge * kWaves * 64) {
+      if (atomic_rank)
+        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptLarge, RANK_ATOMIC>), grid, block, 0, s, d_in, d_out, tmp, nn,
+                           d, plan, base_d, st_d, tctr);
+      else
+        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptLarge, RANK_MATCH>), grid, block, 0, s, d_in, d_out, tmp, nn,
+                           d, plan, base_d, st_d, tctr);
+    } else {
+      if (atomic_rank)
+        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptSmall, RANK_ATOMIC>), grid, block, 0, s, d_in, d_out, tmp, nn,
+                           d, plan, base_d, st_d, tctr);
+      else
+        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptSmall, RANK_MATCH>), grid, block, 0, s, d_in, d_out, tmp, nn,
+                           d, plan, base_d, st_d, tctr);
+    }
     prof_end(s);
     ap_status st = check_launch(s, "k_pass");
     if (st != AP_OK) return st;
@@ -172,21 +247,22 @@ ap_status fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s) {
 }
 
 // Inspection entry point: k_hist_plan alone with a given digit width, on a small per-device
-// control block (hist up to 6144 counters, base, plan, done) that stays zero between calls.
+// control block (4 copies of up to 8192 counters, base, plan, done) that stays zero between calls.
 template <int BITS>
 static ap_status launch_plan_only(const uint32_t* d_in, uint32_t n, uint32_t* ctl, uint32_t* d_hist,
                                   uint32_t* d_plan, hipStream_t s) {
   constexpr int R = 1 << BITS, D = (32 + BITS - 1) / BITS;
-  uint32_t* hist = ctl;
-  uint32_t* base = ctl + 8192;
-  uint32_t* plan = ctl + 16384;
-  uint32_t* done = ctl + 16384 + PL_WORDS;
+  uint32_t* hist = ctl;                          // 4 x 8192 words
+  uint32_t* base = ctl + 4 * 8192;               // 8192 words
+  uint32_t* plan = ctl + 5 * 8192;               // PL_WORDS
+  uint32_t* done = ctl + 5 * 8192 + PL_WORDS;
   const int cus = device_cus();
   uint32_t g = (uint32_t)std::min<size_t>(((size_t)n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16),
                                           (size_t)2 * cus);
   g = std::max<uint32_t>(g, 1);
-  hipLaunchKernelGGL((k_hist_plan<BITS, kHistThreads>), dim3(g), dim3(kHistThreads), 0, s, d_in, n, hist, base,
-                     plan, done, (uint4*)nullptr, 0u, 0, d_hist);
+  hipLaunchKernelGGL((k_hist_plan<BITS, kHistThreads, hist_lcopies<BITS>()>), dim3(g), dim3(kHistThreads), 0, s,
+                     d_in, n, hist, base,
+                     plan, done, (uint4*)nullptr, 0u, 0, d_hist, 4u);
   ap_status st = check_launch(s, "k_hist_plan");
   if (st != AP_OK || !d_plan) return st;
   // d_plan[d] = run flag of pass d, d_plan[D] = number of passes
@@ -209,9 +285,9 @@ ap_status enqueue_digit_plan(const uint32_t* d_in, size_t n, int bits, uint32_t*
     if ((int)ctl_per_dev.size() <= dev) ctl_per_dev.resize(dev + 1, nullptr);
     if (!ctl_per_dev[dev]) {
       uint32_t* p = nullptr;
-      e = hipMalloc(&p, sizeof(uint32_t) * (16384 + 256));
+      e = hipMalloc(&p, sizeof(uint32_t) * (5 * 8192 + 256));
       if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan control block)");
-      ap_status st = fill_u32(p, 0u, 16384 + 256, s);
+      ap_status st = fill_u32(p, 0u, 5 * 8192 + 256, s);
       if (st != AP_OK) return st;
       ctl_per_dev[dev] = p;
     }
@@ -273,6 +349,8 @@ ap_status cached_workspace(size_t need, hipStream_t s, void** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  ap_status cst = check_lane_order(s);
+  if (cst != AP_OK) return cst;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   for (auto& c : g_cache) {
     if (c.dev == dev && c.stream == s) {
@@ -344,6 +422,8 @@ ap_status ap_workspace_init(void* d_ws, size_t ws_bytes, void* stream) {
   const size_t need = layout_for(0).init_bytes;
   if (!d_ws || ws_bytes < need) return fail(AP_ERR_INVALID, "workspace too small for its control block");
   if ((uintptr_t)d_ws & 255u) return fail(AP_ERR_INVALID, "workspace must be 256-byte aligned");
+  ap_status st = check_lane_order(static_cast<hipStream_t>(stream));
+  if (st != AP_OK) return st;
   return fill_u32(static_cast<uint32_t*>(d_ws), 0u, need / 4, static_cast<hipStream_t>(stream));
 }
 
@@ -378,5 +458,13 @@ ap_status ap_digit_plan_u32(const uint32_t* d_in, size_t n, int digit_bits, uint
 }
 
 ap_status ap_release_cache(void) { return release_cache(); }
+
+int ap_rank_check_state(void) { return lane_order_state(); }
+
+ap_status ap_set_rank_mode(int mode) {
+  if (mode != 0 && mode != 1) return fail(AP_ERR_INVALID, "rank mode must be 0 (auto) or 1 (match)");
+  set_rank_mode(mode);
+  return AP_OK;
+}
 
 }  // extern "C"

@@ -24,6 +24,8 @@ ap_status fail(ap_status st, const char* fmt, ...);
 ap_status hip_fail(hipError_t e, const char* what);
 ap_status check_launch(hipStream_t s, const char* what);
 int device_cus();
+bool lane_order_ok();
+ap_status check_lane_order(hipStream_t s);
 ap_status fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // Kernel timing: prof_begin/prof_end bracket one launch when profiling is on for this thread.
 void prof_begin(int kind, hipStream_t s);

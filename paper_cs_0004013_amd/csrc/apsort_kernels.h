@@ -118,33 +118,41 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t coun
 // ------------------------------------------------------------------------------------------------
 // A1 + A2: bucket counts of all digits in one read, then (last workgroup) constant-digit flags,
 // exclusive scans and the pass plan.
-//   g_hist   D*R counters, zero on entry, left zero on exit (the last workgroup clears them)
+//   g_hist   ncopies * D*R counters, zero on entry, left zero on exit (the last workgroup clears
+//            them); workgroup g adds into copy g % ncopies so that fewer workgroups contend for
+//            one counter
 //   done     workgroup-completion counter, zero on entry and on exit
-//   zero_ptr/zero_words  scan state of the passes (tile counters + status words), cleared here
+//   zero_ptr/zero_vec4  scan state of the passes (tile counters + status words), cleared here
 //   out_hist optional copy of the final counts (inspection entry point)
+// Inside a workgroup the counts go to LCOPIES copies in LDS, lane l using copy l % LCOPIES, so that
+// lanes holding equal digits (clustered keys) collide on one LDS word at most 64/LCOPIES-fold.
+// Copies sit HW+1 words apart so that equal buckets of different copies fall in different banks.
 // ------------------------------------------------------------------------------------------------
-template <int BITS, int THREADS>
+template <int BITS, int THREADS, int LCOPIES>
 __global__ __launch_bounds__(THREADS) void k_hist_plan(
     const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restrict__ g_hist,
     uint32_t* __restrict__ g_base, uint32_t* __restrict__ plan, uint32_t* __restrict__ done,
-    uint4* __restrict__ zero_ptr, uint32_t zero_vec4, int inplace, uint32_t* __restrict__ out_hist) {
+    uint4* __restrict__ zero_ptr, uint32_t zero_vec4, int inplace, uint32_t* __restrict__ out_hist,
+    uint32_t ncopies) {
   constexpr int R = 1 << BITS;
   constexpr int D = (32 + BITS - 1) / BITS;
   constexpr int HW = D * R;
-  __shared__ uint32_t h[HW];
+  constexpr int CS = HW + 1;  // copy stride
+  __shared__ uint32_t h[LCOPIES * CS];
   __shared__ uint32_t s_const[kMaxDigits];
   __shared__ uint32_t s_scan[THREADS / 64];
   __shared__ int s_last;
 
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < HW; i += THREADS) h[i] = 0u;
+  for (uint32_t i = tid; i < LCOPIES * CS; i += THREADS) h[i] = 0u;
   const uint32_t gtid = blockIdx.x * THREADS + tid, gstride = gridDim.x * THREADS;
   for (uint32_t i = gtid; i < zero_vec4; i += gstride) zero_ptr[i] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
 
+  uint32_t* __restrict__ hc = h + (tid % LCOPIES) * CS;
   auto count = [&](uint32_t k) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) atomicAdd(&h[d * R + ((k >> (d * BITS)) & (R - 1))], 1u);
+    for (int d = 0; d < D; ++d) atomicAdd(&hc[d * R + ((k >> (d * BITS)) & (R - 1))], 1u);
   };
   uint32_t head = (uint32_t)(((16u - ((uintptr_t)keys & 15u)) & 15u) >> 2);
   if (head > n) head = n;
@@ -165,24 +173,41 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
   }
   for (uint32_t j = head + nv * 4 + gtid; j < n; j += gstride) count(keys[j]);
   __syncthreads();
+  uint32_t* __restrict__ mine = g_hist + (size_t)(blockIdx.x % ncopies) * HW;
   for (uint32_t j = tid; j < HW; j += THREADS) {
-    const uint32_t c = h[j];
-    if (c) add_agent(&g_hist[j], c);
+    uint32_t c = 0u;
+#pragma unroll
+    for (int cp = 0; cp < LCOPIES; ++cp) c += h[cp * CS + j];
+    if (c) add_agent(&mine[j], c);
   }
-  __threadfence();
+  // Last-workgroup-done: the barrier makes every thread's adds complete before thread 0's
+  // release fence and completion count; the last workgroup's acquire fence pairs with those
+  // fences.  One thread per workgroup fences (a device-scope fence writes back and invalidates
+  // the L2, so it is kept off the other threads).
   __syncthreads();
-  if (tid == 0) s_last = (add_agent(done, 1u) == gridDim.x - 1);
+  if (tid == 0) {
+    __threadfence();
+    s_last = (add_agent(done, 1u) == gridDim.x - 1);
+    if (s_last) __threadfence();
+  }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
 
   // ---- last workgroup: every count is in g_hist ----
   if (tid < kMaxDigits) s_const[tid] = 0u;
   __syncthreads();
+  const uint32_t used = gridDim.x < ncopies ? gridDim.x : ncopies;
   for (uint32_t j = tid; j < HW; j += THREADS) {
-    const uint32_t c = ld_agent(&g_hist[j]);
+    uint32_t c = 0u;
+    for (uint32_t cp0 = 0; cp0 < used; cp0 += 8) {
+      uint32_t part[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) part[q] = (cp0 + q < used) ? ld_agent(&g_hist[(size_t)(cp0 + q) * HW + j]) : 0u;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) c += part[q];
+    }
+    for (uint32_t cp = 0; cp < used; ++cp) g_hist[(size_t)cp * HW + j] = 0u;
     h[j] = c;
-    st_agent(&g_hist[j], 0u);
     if (out_hist) out_hist[j] = c;
     if (c == n) s_const[j / R] = 1u;  // one bucket holds every key: the digit is constant
   }
@@ -216,12 +241,55 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
   }
 }
 
+// Rank primitives for the digit pass (RANK template argument of k_pass).
+enum RankKind : int {
+  RANK_ATOMIC = 0,  // LDS add-with-return on per-wave counters; relies on the LDS servicing the
+                    // conflicting lanes of one instruction in ascending lane order (checked on the
+                    // device by k_lane_order_probe before this kind is used)
+  RANK_MATCH = 1    // per-wave LDS lane masks (OR, read, clear) + leader update; order-agnostic
+};
+
+// Checks the lane-order property RANK_ATOMIC relies on: for many address patterns (all lanes on
+// one word, few words, many words, partial exec masks), lane l must get back the number of lower
+// active lanes that hit the same word.  out[0] is left 0 when every check passes.
+__global__ __launch_bounds__(256) void k_lane_order_probe(uint32_t* __restrict__ out, uint32_t rounds) {
+  __shared__ uint32_t cnt[4][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t bad = 0u;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    for (int i = lane; i < 256; i += 64) cnt[w][i] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    // pattern: address from a hash of (round, wave, lane) reduced to 1..256 distinct words
+    uint32_t x = (r * 0x9E3779B9u) ^ ((uint32_t)(blockIdx.x * 4 + w) * 0x85EBCA6Bu) ^ ((uint32_t)lane * 0xC2B2AE35u);
+    x ^= x >> 15; x *= 0x2C1B3C6Du; x ^= x >> 12;
+    const uint32_t span = 1u << (r % 9);                 // 1, 2, 4, ..., 256 distinct words
+    const uint32_t a = x & (span - 1u);
+    const bool act = ((r % 5) != 4) || ((x >> 20) & 1u);  // every fifth round: random exec mask
+    uint32_t got = 0u;
+    if (act) got = __hip_atomic_fetch_add(&cnt[w][a], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    // expected rank: active lower lanes with the same word
+    uint32_t want = 0u;
+    for (int l = 0; l < 64; ++l) {
+      const uint32_t al = __shfl(a, l, 64);
+      const bool actl = __shfl((int)act, l, 64) != 0;
+      want += (l < lane && actl && al == a) ? 1u : 0u;
+    }
+    if (act && got != want) bad = 1u;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (bad) atomicOr(out, 1u);
+}
+
 // ------------------------------------------------------------------------------------------------
 // A3-A6: one digit pass over one tile of T = WAVES*64*IPT keys.
 // Keys are taken wave-striped (key j of lane l of wave w sits at w*64*IPT + j*64 + l), which is
 // memory order in (w, j, l) order, so ranking sub-step j of every wave in order is stable.
+// Order of work in a tile: claim a tile id once every wave of the workgroup is running (a tile
+// claimed early by a workgroup whose other waves start late would hold up every later tile's
+// look-back); load; rank; publish the tile's bucket counts; tile-local scan; reorder the keys in
+// LDS; look back for the global bucket starts; write the reordered keys out.
 // ------------------------------------------------------------------------------------------------
-template <int BITS, int WAVES, int IPT>
+template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN = 4>
 __global__ __launch_bounds__(WAVES * 64) void k_pass(
     const uint32_t* in, uint32_t* out, uint32_t* tmp, uint32_t n, int d,
     const uint32_t* __restrict__ plan, const uint32_t* __restrict__ g_base,
@@ -241,10 +309,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   __shared__ uint32_t s_stage[T];        // keys in tile-sorted order
   __shared__ uint32_t s_scan[THREADS / 64];
   __shared__ uint32_t s_tile;
+  __shared__ uint64_t s_bins[RANK == RANK_MATCH ? WAVES * R : 1];  // per-wave bucket lane masks
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) s_tile = add_agent(tile_ctr + d, 1u);
   for (int j = tid; j < WAVES * R; j += THREADS) s_cnt[j] = 0u;
+  if constexpr (RANK == RANK_MATCH)
+    for (int j = tid; j < WAVES * R; j += THREADS) s_bins[j] = 0ull;
+  __syncthreads();
+  if (tid == 0) s_tile = add_agent(tile_ctr + d, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
   const uint32_t tbase = tile * (uint32_t)T;
@@ -266,14 +338,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   // ---- A4: stable rank within the wave's keys ----
   uint32_t r[IPT];
   uint32_t* cnt = s_cnt + wid * R;
+  if constexpr (RANK == RANK_ATOMIC) {
+    // LDS executes one wave's instructions in order and services the conflicting lanes of one
+    // instruction in lane order, so the value returned to a key is the number of keys of this
+    // wave, earlier in memory order, with the same digit.
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const uint32_t v = (k[j] >> shift) & (R - 1);
-    const uint64_t m = match_any<BITS>(v);
-    const uint32_t peers = lanes_below(m);
-    const uint32_t c = cnt[v];
-    r[j] = c + peers;
-    if (peers == 0u) cnt[v] = c + (uint32_t)__popcll(m);
+    for (int j = 0; j < IPT; ++j) {
+      const uint32_t v = (k[j] >> shift) & (R - 1);
+      r[j] = __hip_atomic_fetch_add(&cnt[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+  } else {
+    // Every lane ORs its lane bit into its bucket's 64-bit word, reads the word back (the lanes of
+    // this sub-step sharing the bucket) and clears it; the lowest such lane updates the counter.
+    uint64_t* bins = s_bins + wid * R;
+    const uint64_t mybit = 1ull << lane;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const uint32_t v = (k[j] >> shift) & (R - 1);
+      __hip_atomic_fetch_or(&bins[v], mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      const uint64_t m = __hip_atomic_load(&bins[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __hip_atomic_store(&bins[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      const uint32_t peers = lanes_below(m);
+      const uint32_t c = cnt[v];
+      r[j] = c + peers;
+      if (peers == 0u) cnt[v] = c + (uint32_t)__popcll(m);
+    }
   }
   __syncthreads();
 
@@ -298,6 +387,23 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
     }
   }
   lds_exclusive_scan<R, THREADS>(s_delta, s_scan);  // s_delta = tile-local bucket starts
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int b = tid + i * THREADS;
+    if (b < R) {
+      const uint32_t lb = s_delta[b];
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) s_cnt[w * R + b] += lb;
+    }
+  }
+  __syncthreads();
+
+  // ---- A5 (first half): reorder the tile in LDS; independent of the global offsets ----
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const uint32_t v = (k[j] >> shift) & (R - 1);
+    s_stage[cnt[v] + r[j]] = k[j];
+  }
 
   // ---- A3: decoupled look-back for each bucket's global start ----
 #pragma unroll
@@ -308,36 +414,40 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
       if (tile == 0u) {
         excl = g_base[b];
       } else {
+        // Sum the published counts of the preceding tiles, newest first, until one of them has
+        // published its inclusive prefix; LB_WIN status words (one per preceding tile) are
+        // fetched per round trip.
         excl = 0u;
-        uint32_t p = tile - 1;
+        int p = (int)tile - 1;
         while (true) {
-          const uint32_t s = ld_agent(status + (size_t)p * R + b);
-          const uint32_t f = s & kFlagMask;
-          if (f == 0u) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
+          uint32_t sv[LB_WIN];
+#pragma unroll
+          for (int q = 0; q < LB_WIN; ++q) sv[q] = (p - q >= 0) ? ld_agent(status + (size_t)(p - q) * R + b) : 0u;
+          int used = 0;
+          bool done = false;
+#pragma unroll
+          for (int q = 0; q < LB_WIN; ++q) {
+            if (!done && used == q) {
+              const uint32_t f = sv[q] & kFlagMask;
+              if (f != 0u) {
+                excl += sv[q] & kValueMask;
+                ++used;
+                done = (f == kFlagPrefix);
+              }
+            }
           }
-          excl += s & kValueMask;
-          if (f == kFlagPrefix) break;
-          --p;
+          if (done) break;
+          p -= used;
+          if (used == 0) __builtin_amdgcn_s_sleep(1);
         }
         st_agent(status + (size_t)tile * R + b, kFlagPrefix | (excl + tot[i]));
       }
-      const uint32_t lb = s_delta[b];
-#pragma unroll
-      for (int w = 0; w < WAVES; ++w) s_cnt[w * R + b] += lb;
-      s_delta[b] = excl - lb;
+      s_delta[b] = excl - s_delta[b];
     }
   }
   __syncthreads();
 
-  // ---- A5: reorder through LDS, then coalesced scatter ----
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const uint32_t v = (k[j] >> shift) & (R - 1);
-    s_stage[cnt[v] + r[j]] = k[j];
-  }
-  __syncthreads();
+  // ---- A5 (second half): coalesced scatter; runs of one bucket go to consecutive addresses ----
   const uint32_t nvalid = (n - tbase) < (uint32_t)T ? (n - tbase) : (uint32_t)T;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {

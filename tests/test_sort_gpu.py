@@ -188,3 +188,22 @@ def test_invalid_args_raise():
         binding.ap_sort_u32(base[0:100], base[1:101], 64)      # partial overlap
     with pytest.raises(binding.ApError):
         binding.ap_sort_u32(base[0:100], base[0:100], 0)       # P < 1
+
+
+def test_rank_self_check_passed():
+    """The device check of the LDS lane-order property ran and passed, so the atomic rank is used."""
+    from paper_cs_0004013_amd import binding
+    _check(inputs.keyset("a", 5000, 1).keys)
+    assert binding.ap_rank_check_state() == 1
+
+
+@pytest.mark.parametrize("dist", ["a", "d", "e"])
+@pytest.mark.parametrize("n", [12_345, (1 << 22) + 77])
+def test_match_rank_path(dist, n):
+    """The order-agnostic mask rank gives the same (oracle) result."""
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_rank_mode(1)
+    try:
+        _check(inputs.keyset(dist, n, 21).keys)
+    finally:
+        binding.ap_set_rank_mode(0)
