@@ -118,6 +118,119 @@ ap_status ap_digit_plan_u32(const uint32_t *d_in, size_t n, int digit_bits,
                             uint32_t *d_hist, uint32_t *d_plan, void *stream);
 
 /*
+ * ap_sort_u32_segmented -- sort many independent arrays (segments) of one
+ * buffer in place, in one launch sequence.
+ *
+ * Segment s is d_keys[d_offsets[s] .. d_offsets[s+1]), s = 0..nseg-1; each is
+ * sorted independently into nondecreasing order, as each AP1000 cell sorts
+ * its own keys in the local-sort phase (Sec. 3.3, LSD radix sort of
+ * Sec. 3.3.1).  Keys outside every segment are not touched.
+ *
+ *   d_keys     n_total keys (device), sorted in place segment by segment.
+ *   n_total    number of keys in d_keys, < AP_MAX_KEYS; every offset must be
+ *              <= n_total.
+ *   d_offsets  nseg + 1 uint32_t offsets (device), nondecreasing.
+ *   nseg       number of segments, >= 0.
+ *   d_status   optional device uint32_t: set to 0 when the offsets are valid,
+ *              to AP_ERR_INVALID when some segment has a decreasing or
+ *              out-of-range offset (such segments are left unsorted).  The
+ *              offsets live on the device, so this check completes with the
+ *              stream work rather than at the call.
+ *
+ * One workgroup sorts each segment: segments that fit one tile are sorted in
+ * registers and LDS (one read and one write of each key); longer ones by the
+ * same workgroup with a histogram sweep and one sweep per non-constant digit.
+ * Segments are scheduled longest first by a persistent kernel.  No host
+ * synchronisation; on a non-default stream the launch sequence is captured
+ * into a hipGraph and replayed while the arguments repeat.  Scratch memory
+ * (4 * n_total bytes + 4 * nseg bytes + 256) is cached per device and stream.
+ */
+ap_status ap_sort_u32_segmented(uint32_t *d_keys, size_t n_total,
+                                const uint32_t *d_offsets, int nseg,
+                                uint32_t *d_status, void *stream);
+
+/* ap_segmented_workspace_bytes -- scratch size of a segmented call. */
+size_t ap_segmented_workspace_bytes(size_t n_total, int nseg);
+
+/*
+ * Segmented-sort kernel configuration (digit width, waves per workgroup, keys
+ * per lane), chosen by the tuner: ap_segmented_num_configs() configurations
+ * are compiled in; ap_segmented_set_config(i) selects one for later calls
+ * (process-wide; index 0 is the default).
+ */
+int ap_segmented_num_configs(void);
+ap_status ap_segmented_set_config(int cfg);
+
+/*
+ * Request server: sort requests from any number of host threads, batched as
+ * they arrive (continuous batching) and run on several streams at once.
+ *
+ * A request has the contract of ap_sort_u32 (d_in, d_out, n, P, splitters).
+ * Submission is non-blocking and returns a ticket; the request is queued,
+ * admitted when its scratch fits the memory budget of a free slot, and run:
+ * requests shorter than alone_min_keys are batched into one launch of the
+ * persistent segmented kernel (each request sorted by one workgroup, straight
+ * from its input to its output buffer), longer ones run alone through the
+ * device-wide sort.  Requests that arrive while slots are busy join the next
+ * batch formed on a slot that frees up.  The caller keeps every buffer alive
+ * until its ticket completes.
+ *
+ *   hbm_budget_bytes  scratch memory of the server (split evenly over the
+ *                     slots and allocated at creation); default 64 GiB.
+ *   num_streams       slots = concurrent batches; default 4.
+ *   max_batch         requests per batch; default 256.
+ *   max_queue         queued requests before AP_ERR_QUEUE_FULL; default 65536.
+ *   alone_min_keys    requests with n >= this run alone; default 2^20.
+ * Zero fields take the default.
+ *
+ * ap_server_submit: AP_ERR_INVALID for bad arguments, AP_ERR_BUDGET when the
+ *   request can never fit one slot's scratch, AP_ERR_QUEUE_FULL when the queue
+ *   is full.  Nothing is queued then.
+ * ap_server_wait: the ticket's final status (AP_OK, AP_ERR_DEVICE when its
+ *   device work failed, AP_ERR_CANCELLED when the server was destroyed before
+ *   it ran), or AP_ERR_TIMEOUT after timeout_us microseconds (< 0: no limit).
+ *   A ticket whose final status has been returned is forgotten.
+ * ap_server_poll: like ap_server_wait with a zero timeout.
+ * ap_server_get_stats: counters and submit-to-completion latency percentiles
+ *   of the completed requests (since creation or the last reset).
+ * ap_server_destroy: cancels queued requests, waits for running ones, frees
+ *   everything.  No other call on the server may run concurrently with it.
+ * ap_server_submit_flags: ap_server_submit with flags; AP_SUBMIT_INJECT_FAULT
+ *   (testing) makes that one request fail with AP_ERR_DEVICE without running.
+ */
+typedef struct {
+    size_t hbm_budget_bytes;
+    int num_streams;
+    int max_batch;
+    int max_queue;
+    size_t alone_min_keys;
+} ap_server_cfg;
+
+typedef struct {
+    uint64_t submitted, completed, failed, cancelled, batches, alone, keys;
+    uint64_t latency_samples;
+    double p50_us, p99_us, mean_us, max_us;
+} ap_server_stats;
+
+typedef struct ap_server ap_server;
+
+#define AP_SUBMIT_INJECT_FAULT 1u
+
+ap_status ap_server_create(const ap_server_cfg *cfg, ap_server **out);
+ap_status ap_server_submit(ap_server *s, const uint32_t *d_in, uint32_t *d_out,
+                           size_t n, int P, uint32_t *d_splitters,
+                           uint64_t *ticket);
+ap_status ap_server_submit_flags(ap_server *s, const uint32_t *d_in,
+                                 uint32_t *d_out, size_t n, int P,
+                                 uint32_t *d_splitters, unsigned flags,
+                                 uint64_t *ticket);
+ap_status ap_server_wait(ap_server *s, uint64_t ticket, int64_t timeout_us);
+ap_status ap_server_poll(ap_server *s, uint64_t ticket);
+ap_status ap_server_get_stats(ap_server *s, ap_server_stats *out,
+                              int reset_latencies);
+ap_status ap_server_destroy(ap_server *s);
+
+/*
  * ap_release_cache -- free the scratch memory cached for ap_sort_u32 on the
  * current device (all streams).  Synchronises the device first.
  */

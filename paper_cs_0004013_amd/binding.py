@@ -18,6 +18,17 @@ STATUS = {0: "AP_OK", 1: "AP_ERR_INVALID", 2: "AP_ERR_NOMEM", 3: "AP_ERR_HIP", 4
           5: "AP_ERR_QUEUE_FULL", 6: "AP_ERR_TIMEOUT", 7: "AP_ERR_DEVICE", 8: "AP_ERR_CANCELLED"}
 MAX_KEYS = 1 << 30
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("num_streams", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("max_queue", ctypes.c_int), ("alone_min_keys", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "failed", "cancelled", "batches", "alone",
+                                              "keys", "latency_samples")] + \
+               [(f, ctypes.c_double) for f in ("p50_us", "p99_us", "mean_us", "max_us")]
+
+
 # (name, restype, argtypes) of every exported entry point
 _VP, _SZ, _I, _U64P = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
 SIGNATURES = [
@@ -29,6 +40,17 @@ SIGNATURES = [
     ("ap_release_cache", _I, []),
     ("ap_profile_enable", _I, [_I]),
     ("ap_profile_read", _I, [ctypes.POINTER(ctypes.c_double), _U64P, _I]),
+    ("ap_sort_u32_segmented", _I, [_VP, _SZ, _VP, _I, _VP, _VP]),
+    ("ap_segmented_workspace_bytes", _SZ, [_SZ, _I]),
+    ("ap_segmented_num_configs", _I, []),
+    ("ap_segmented_set_config", _I, [_I]),
+    ("ap_server_create", _I, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)]),
+    ("ap_server_submit", _I, [_VP, _VP, _VP, _SZ, _I, _VP, _U64P]),
+    ("ap_server_submit_flags", _I, [_VP, _VP, _VP, _SZ, _I, _VP, ctypes.c_uint, _U64P]),
+    ("ap_server_wait", _I, [_VP, ctypes.c_uint64, ctypes.c_int64]),
+    ("ap_server_poll", _I, [_VP, ctypes.c_uint64]),
+    ("ap_server_get_stats", _I, [_VP, ctypes.POINTER(ServerStats), _I]),
+    ("ap_server_destroy", _I, [_VP]),
     ("ap_rank_check_state", _I, []),
     ("ap_set_rank_mode", _I, [_I]),
     ("ap_last_error", ctypes.c_char_p, []),
@@ -166,6 +188,92 @@ def ap_profile_read() -> tuple[list[float], list[int]]:
     cnt = (ctypes.c_uint64 * AP_NKINDS)()
     check(lib().ap_profile_read(ms, cnt, AP_NKINDS), "ap_profile_read")
     return list(ms), list(cnt)
+
+
+def ap_sort_u32_segmented(t_keys, t_offsets, t_status=None, stream=None) -> None:
+    """Sort every segment t_keys[t_offsets[s]:t_offsets[s+1]] in place (batched form)."""
+    nseg = t_offsets.numel() - 1
+    if nseg < 0:
+        raise ValueError("offsets need at least one entry")
+    n = t_keys.numel()
+    st = lib().ap_sort_u32_segmented(_keys_ptr(t_keys, "keys") if n else None, n,
+                                     _keys_ptr(t_offsets, "offsets"), nseg,
+                                     _keys_ptr(t_status, "status") if t_status is not None else None,
+                                     _stream(stream))
+    check(st, "ap_sort_u32_segmented")
+
+
+def ap_segmented_num_configs() -> int:
+    return int(lib().ap_segmented_num_configs())
+
+
+def ap_segmented_set_config(cfg: int) -> None:
+    check(lib().ap_segmented_set_config(cfg), "ap_segmented_set_config")
+
+
+AP_SUBMIT_INJECT_FAULT = 1
+
+
+class Server:
+    """Request server (ap_server_*): submit sorts of device buffers, wait on tickets."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, num_streams: int = 0, max_batch: int = 0, max_queue: int = 0,
+                 alone_min_keys: int = 0):
+        cfg = ServerCfg(hbm_budget_bytes, num_streams, max_batch, max_queue, alone_min_keys)
+        h = ctypes.c_void_p()
+        check(lib().ap_server_create(ctypes.byref(cfg), ctypes.byref(h)), "ap_server_create")
+        self._h = h
+
+    def submit_ptr(self, in_ptr: int, out_ptr: int, n: int, P: int, spl_ptr: int | None = None,
+                   flags: int = 0) -> int:
+        """Submit by raw device pointers; returns the ticket (raises on rejection)."""
+        t = ctypes.c_uint64()
+        st = lib().ap_server_submit_flags(self._h, in_ptr or None, out_ptr or None, n, P, spl_ptr or None, flags,
+                                          ctypes.byref(t))
+        check(st, "ap_server_submit")
+        return t.value
+
+    def try_submit_ptr(self, in_ptr: int, out_ptr: int, n: int, P: int, spl_ptr: int | None = None,
+                       flags: int = 0) -> tuple[int, int]:
+        """(status, ticket) without raising."""
+        t = ctypes.c_uint64()
+        st = lib().ap_server_submit_flags(self._h, in_ptr or None, out_ptr or None, n, P, spl_ptr or None, flags,
+                                          ctypes.byref(t))
+        return st, t.value
+
+    def submit(self, t_in, t_out, P: int = 64, t_splitters=None, flags: int = 0) -> int:
+        n = t_in.numel()
+        return self.submit_ptr(_keys_ptr(t_in, "in") if n else 0, _keys_ptr(t_out, "out") if n else 0, n, P,
+                               _keys_ptr(t_splitters, "splitters") if t_splitters is not None else 0, flags)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> int:
+        """Final status of the ticket (AP_OK = 0) or AP_ERR_TIMEOUT (6)."""
+        return int(lib().ap_server_wait(self._h, ticket, timeout_us))
+
+    def poll(self, ticket: int) -> int:
+        return int(lib().ap_server_poll(self._h, ticket))
+
+    def stats(self, reset_latencies: bool = False) -> dict:
+        st = ServerStats()
+        check(lib().ap_server_get_stats(self._h, ctypes.byref(st), 1 if reset_latencies else 0), "ap_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            check(lib().ap_server_destroy(self._h), "ap_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ap_rank_check_state() -> int:

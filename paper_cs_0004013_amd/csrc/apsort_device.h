@@ -1,0 +1,100 @@
+// Device-side helpers shared by every kernel of libapsort.so: plan words, look-back status word
+// format, memory-scope helpers, wave primitives and an LDS scan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aps {
+
+// ---- pass plan, written by the last workgroup of k_hist_plan, read by k_pass / k_finalize ----
+constexpr int kMaxDigits = 8;  // digit width >= 4 bits
+enum PlanWord : int {
+  PL_RUN = 0,              // [kMaxDigits] 1 when pass d runs
+  PL_SRC = 8,              // [kMaxDigits] buffer selector read by pass d
+  PL_DST = 16,             // [kMaxDigits] buffer selector written by pass d
+  PL_NPASS = 24,           // number of passes that run
+  PL_FINAL = 25,           // selector of the buffer holding the sorted keys after the last pass
+  PL_COPY = 26,            // 1 when k_finalize must copy PL_FINAL into the output
+  PL_WORDS = 32
+};
+enum BufSel : uint32_t { SEL_IN = 0, SEL_OUT = 1, SEL_TMP = 2 };
+
+// ---- look-back status word: 2-bit state | 30-bit count ----
+constexpr uint32_t kFlagMask = 3u << 30;
+constexpr uint32_t kFlagAgg = 1u << 30;     // tile's own bucket count is published
+constexpr uint32_t kFlagPrefix = 2u << 30;  // inclusive prefix through this tile is published
+constexpr uint32_t kValueMask = (1u << 30) - 1;
+
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add_agent(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Number of set bits of m in lanes below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Mask of the lanes of the (fully active) wave whose BITS-bit value equals the caller's.
+// One ballot per bit: keep the lanes that agree with this lane on every bit.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_any(uint32_t v) {
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const bool bit = (v >> b) & 1u;
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+// In-place exclusive scan of a[0..N) in LDS by the whole workgroup; returns the total.
+// scratch needs THREADS/64 words.  Starts and ends with a workgroup barrier.
+template <int N, int THREADS>
+__device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t* scratch) {
+  constexpr int C = (N + THREADS - 1) / THREADS;
+  constexpr int W = THREADS / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __syncthreads();
+  uint32_t local[C];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int idx = tid * C + c;
+    local[c] = idx < N ? a[idx] : 0u;
+    sum += local[c];
+  }
+  uint32_t x = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) scratch[wid] = x;
+  __syncthreads();
+  uint32_t wpre = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t s = scratch[w];
+    wpre += (w < wid) ? s : 0u;
+    total += s;
+  }
+  uint32_t run = wpre + x - sum;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int idx = tid * C + c;
+    if (idx < N) a[idx] = run;
+    run += local[c];
+  }
+  __syncthreads();
+  return total;
+}
+
+}  // namespace aps

@@ -30,6 +30,17 @@ ap_status fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
 // Kernel timing: prof_begin/prof_end bracket one launch when profiling is on for this thread.
 void prof_begin(int kind, hipStream_t s);
 void prof_end(hipStream_t s);
+bool prof_active();
+
+// Segmented sort (apsort_seg.hip), shared with the request server.
+struct SegDesc;
+struct SegCtl;
+void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t nwork, SegCtl* ctl);
+int seg_workgroups(int cfg, uint32_t nwork);
+int seg_tile_keys(int cfg);
+int seg_config();
+ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
+                       const Layout& L, hipStream_t s);
 
 ap_status enqueue_digit_plan(const uint32_t* d_in, size_t n, int bits, uint32_t* d_hist, uint32_t* d_plan,
                              hipStream_t s);

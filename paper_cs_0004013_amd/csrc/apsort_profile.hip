@@ -39,6 +39,8 @@ struct ProfState {
 
 static thread_local ProfState t_prof;
 
+bool prof_active() { return t_prof.on; }
+
 void prof_begin(int kind, hipStream_t s) {
   ProfState& p = t_prof;
   if (!p.on) return;

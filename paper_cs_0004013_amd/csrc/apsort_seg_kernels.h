@@ -1,0 +1,349 @@
+// Device kernels of the batched segmented sort: many independent key arrays (segments) of one
+// buffer, each sorted in place, in one persistent launch.
+//
+// Each segment is sorted by one workgroup, the way each AP1000 cell runs its own local radix sort
+// on the keys it holds (Sec. 3.3 / 3.3.1): a segment that fits in one tile is sorted entirely in
+// registers and LDS (read once, written once); a longer one is sorted by the same workgroup with
+// one LDS histogram sweep over the segment (Sec. 3.2 bucket counts and cumulative totals for all
+// digits) and then, per digit, a sweep over its tiles in order, in which running bucket offsets kept
+// in LDS replace any cross-workgroup scan.  Digits constant over a segment are skipped.  Segments
+// are taken longest first so the longest ones do not finish last.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "apsort.h"
+#include "apsort_device.h"
+#include "apsort_seg_types.h"
+
+namespace aps {
+
+__device__ __forceinline__ int seg_class(uint32_t len) { return 31 - __clz(len); }
+
+// Pass 1: validate offsets, count segments per length class; the last workgroup turns the counts
+// into a longest-first order of classes and reports invalid offsets through d_status.
+__global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict__ off, uint32_t nseg,
+                                                     uint32_t n_total, SegCtl* __restrict__ ctl,
+                                                     uint32_t* __restrict__ d_status) {
+  __shared__ uint32_t s_cnt[kSegBuckets];
+  __shared__ uint32_t s_bad;
+  __shared__ int s_last;
+  const uint32_t tid = threadIdx.x;
+  if (tid < kSegBuckets) s_cnt[tid] = 0u;
+  if (tid == 0) s_bad = 0u;
+  __syncthreads();
+  for (uint32_t s = blockIdx.x * 256 + tid; s < nseg; s += gridDim.x * 256) {
+    const uint32_t a = off[s], b = off[s + 1];
+    if (b < a || b > n_total) {
+      s_bad = 1u;
+      continue;
+    }
+    const uint32_t len = b - a;
+    if (len >= 2) atomicAdd(&s_cnt[seg_class(len)], 1u);
+  }
+  __syncthreads();
+  if (tid < kSegBuckets && s_cnt[tid]) add_agent(&ctl->count[tid], s_cnt[tid]);
+  if (tid == 0 && s_bad) atomicOr(&ctl->bad, 1u);
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    s_last = (add_agent(&ctl->done, 1u) == gridDim.x - 1);
+    if (s_last) __threadfence();
+  }
+  __syncthreads();
+  if (!s_last) return;
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int c = kSegBuckets - 1; c >= 0; --c) {  // longest class first
+      const uint32_t k = ld_agent(&ctl->count[c]);
+      ctl->start[c] = run;
+      run += k;
+    }
+    ctl->nwork = run;
+    ctl->done = 0u;
+    const uint32_t bad = ld_agent(&ctl->bad);
+    if (d_status) d_status[0] = bad ? (uint32_t)AP_ERR_INVALID : 0u;
+  }
+}
+
+// Pass 2: write a descriptor for each valid segment into its class's slots of the work order
+// (in place: src == dst == keys + offset, scratch at the same offset of tmp).
+__global__ __launch_bounds__(256) void k_seg_fill(const uint32_t* __restrict__ off, uint32_t nseg, uint32_t n_total,
+                                                 SegCtl* __restrict__ ctl, uint32_t* keys, uint32_t* tmp,
+                                                 SegDesc* __restrict__ order) {
+  for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < nseg; s += gridDim.x * 256) {
+    const uint32_t a = off[s], b = off[s + 1];
+    if (b < a || b > n_total) continue;
+    const uint32_t len = b - a;
+    if (len < 2) continue;
+    const int c = seg_class(len);
+    SegDesc dsc;
+    dsc.src = keys + a;
+    dsc.dst = keys + a;
+    dsc.tmp = tmp + a;
+    dsc.spl = nullptr;
+    dsc.n = len;
+    dsc.P = 1u;
+    dsc.pad[0] = dsc.pad[1] = 0u;
+    order[ctl->start[c] + add_agent(&ctl->cursor[c], 1u)] = dsc;
+  }
+}
+
+// Shared memory of k_seg_sort.  The histogram copies of the first sweep and the tile buffers of
+// the digit sweeps are never live at the same time.
+template <int BITS, int WAVES, int IPT, int LCOPIES>
+struct SegSmem {
+  static constexpr int R = 1 << BITS;
+  static constexpr int D = (32 + BITS - 1) / BITS;
+  static constexpr int T = WAVES * 64 * IPT;
+  static constexpr int HW = D * R;
+  union U {
+    uint32_t hist[LCOPIES * (HW + 1)];
+    struct P {
+      uint32_t stage[T];
+      uint32_t cnt[WAVES * R];
+    } p;
+  } u;
+  uint32_t base[HW];     // segment-wide exclusive bucket starts, per digit
+  uint32_t running[R];   // next free slot of each bucket in the current digit sweep
+  uint32_t lbase[R];     // tile-local bucket starts
+  uint32_t tot[R];       // tile bucket totals
+  uint32_t scan[WAVES];
+  uint32_t flag[kMaxDigits];
+  uint32_t item;
+};
+
+// Splitters of a sorted segment: splitter p-1 = first key of cell p of P equal cells, all-ones
+// for an empty cell (Sec. 1.1, footnote to Sec. 3.4.2).  Called after a workgroup barrier that
+// follows the segment's last writes.
+template <int THREADS>
+__device__ __forceinline__ void seg_splitters(const SegDesc& dsc, uint32_t len) {
+  if (!dsc.spl) return;
+  __syncthreads();
+  const uint32_t P = dsc.P, q = len / P, r = len % P;
+  for (uint32_t p = threadIdx.x + 1; p < P; p += THREADS) {
+    const uint64_t start = (uint64_t)p * q + (p < r ? p : r);
+    dsc.spl[p - 1] = start < len ? dsc.dst[start] : 0xFFFFFFFFu;
+  }
+}
+
+// Tile rank of the keys k[] (wave-striped order) by the digit at `shift`: per-wave LDS counters
+// with lane-ordered atomics, then per-bucket wave prefixes, tile totals (tot) and tile-local
+// starts (lbase); finally cnt[w][v] holds the tile-local start of wave w's run of bucket v.
+template <int BITS, int WAVES, int IPT, int LCOPIES>
+__device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>& sm, const uint32_t (&k)[IPT],
+                                              uint32_t (&r)[IPT], int shift) {
+  constexpr int R = 1 << BITS, THREADS = WAVES * 64;
+  const int tid = threadIdx.x, wid = tid >> 6;
+  for (int j = tid; j < WAVES * R; j += THREADS) sm.u.p.cnt[j] = 0u;
+  __syncthreads();
+  uint32_t* cnt = sm.u.p.cnt + wid * R;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const uint32_t v = (k[j] >> shift) & (R - 1);
+    r[j] = __hip_atomic_fetch_add(&cnt[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  }
+  __syncthreads();
+  for (int b = tid; b < R; b += THREADS) {
+    uint32_t s = 0u;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      const uint32_t c = sm.u.p.cnt[w * R + b];
+      sm.u.p.cnt[w * R + b] = s;
+      s += c;
+    }
+    sm.tot[b] = s;
+    sm.lbase[b] = s;
+  }
+  lds_exclusive_scan<R, THREADS>(sm.lbase, sm.scan);
+  for (int b = tid; b < R; b += THREADS) {
+    const uint32_t lb = sm.lbase[b];
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) sm.u.p.cnt[w * R + b] += lb;
+  }
+  __syncthreads();
+}
+
+// Persistent segmented sort over the descriptors order[0..nwork), longest first.  nwork is read
+// from ctl when nwork_arg is ~0u (work list built on the device) and taken from the argument
+// otherwise (work list built on the host).
+template <int BITS, int WAVES, int IPT, int LCOPIES>
+__global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restrict__ order, uint32_t nwork_arg,
+                                                        SegCtl* __restrict__ ctl) {
+  using SM = SegSmem<BITS, WAVES, IPT, LCOPIES>;
+  constexpr int R = SM::R, D = SM::D, T = SM::T, HW = SM::HW, THREADS = WAVES * 64;
+  constexpr int CS = HW + 1;
+  __shared__ SM sm;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const uint32_t nwork = nwork_arg == ~0u ? ctl->nwork : nwork_arg;
+
+  while (true) {
+    __syncthreads();
+    if (tid == 0) sm.item = add_agent(&ctl->head, 1u);
+    __syncthreads();
+    const uint32_t item = sm.item;
+    if (item >= nwork) break;
+    const SegDesc dsc = order[item];
+    const uint32_t len = dsc.n;
+
+    if (len <= (uint32_t)T) {
+      // ---------------- whole segment in registers + LDS ----------------
+      uint32_t k[IPT], r[IPT];
+      const uint32_t lb0 = (uint32_t)(wid * 64 * IPT + lane);
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const uint32_t idx = lb0 + j * 64;
+        k[j] = idx < len ? dsc.src[idx] : 0xFFFFFFFFu;
+      }
+      const uint32_t nsent = (uint32_t)T - len;
+#pragma unroll 1
+      for (int d = 0; d < D; ++d) {
+        const int shift = d * BITS;
+        seg_rank_tile<BITS, WAVES, IPT, LCOPIES>(sm, k, r, shift);
+        // constant digit over the segment's keys (sentinels sit in the largest bucket)
+        if (tid == 0) sm.flag[0] = 0u;
+        __syncthreads();
+        const uint32_t vmax = (0xFFFFFFFFu >> shift) & (R - 1);
+        for (int b = tid; b < R; b += THREADS)
+          if (sm.tot[b] - ((uint32_t)b == vmax ? nsent : 0u) == len) sm.flag[0] = 1u;
+        __syncthreads();
+        if (sm.flag[0]) continue;  // uniform across the workgroup
+        uint32_t* cnt = sm.u.p.cnt + wid * R;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const uint32_t v = (k[j] >> shift) & (R - 1);
+          sm.u.p.stage[cnt[v] + r[j]] = k[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) k[j] = sm.u.p.stage[lb0 + j * 64];
+      }
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const uint32_t idx = lb0 + j * 64;
+        if (idx < len) dsc.dst[idx] = k[j];
+      }
+      seg_splitters<THREADS>(dsc, len);
+      continue;
+    }
+
+    // ---------------- longer segment: histogram sweep, then one sweep per digit ----------------
+    const uint32_t* __restrict__ seg = dsc.src;
+    for (int i = tid; i < LCOPIES * CS; i += THREADS) sm.u.hist[i] = 0u;
+    __syncthreads();
+    {
+      uint32_t* hc = sm.u.hist + (tid % LCOPIES) * CS;
+      auto count = [&](uint32_t key) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) atomicAdd(&hc[d * R + ((key >> (d * BITS)) & (R - 1))], 1u);
+      };
+      uint32_t head = (uint32_t)(((16u - ((uintptr_t)seg & 15u)) & 15u) >> 2);
+      if (head > len) head = len;
+      if ((uint32_t)tid < head) count(seg[tid]);
+      const uint4* __restrict__ v4 = reinterpret_cast<const uint4*>(seg + head);
+      const uint32_t nv = (len - head) >> 2;
+      uint32_t i = tid;
+      for (; i + 3 * THREADS < nv; i += 4 * THREADS) {
+        const uint4 x0 = v4[i], x1 = v4[i + THREADS], x2 = v4[i + 2 * THREADS], x3 = v4[i + 3 * THREADS];
+        count(x0.x); count(x0.y); count(x0.z); count(x0.w);
+        count(x1.x); count(x1.y); count(x1.z); count(x1.w);
+        count(x2.x); count(x2.y); count(x2.z); count(x2.w);
+        count(x3.x); count(x3.y); count(x3.z); count(x3.w);
+      }
+      for (; i < nv; i += THREADS) {
+        const uint4 x = v4[i];
+        count(x.x); count(x.y); count(x.z); count(x.w);
+      }
+      for (uint32_t j = head + nv * 4 + tid; j < len; j += THREADS) count(seg[j]);
+    }
+    if (tid < kMaxDigits) sm.flag[tid] = 0u;
+    __syncthreads();
+    for (int j = tid; j < HW; j += THREADS) {
+      uint32_t c = 0u;
+#pragma unroll
+      for (int cp = 0; cp < LCOPIES; ++cp) c += sm.u.hist[cp * CS + j];
+      sm.base[j] = c;
+      if (c == len) sm.flag[j / R] = 1u;  // constant digit
+    }
+#pragma unroll 1
+    for (int d = 0; d < D; ++d) lds_exclusive_scan<R, THREADS>(sm.base + d * R, sm.scan);
+
+    // Sweep buffers: the first sweep reads src; the sweeps alternate between dst and tmp so that the
+    // last one writes dst.  In place (src == dst) the first sweep must write tmp, and an odd number
+    // of sweeps then ends in tmp, which is copied back.
+    uint32_t npass = 0;
+    for (int d = 0; d < D; ++d) npass += sm.flag[d] ? 0u : 1u;
+    const bool inplace = dsc.src == dsc.dst;
+    const uint32_t* src = seg;
+    uint32_t* dst = (inplace || !(npass & 1u)) ? dsc.tmp : dsc.dst;
+    uint32_t* other = (dst == dsc.tmp) ? dsc.dst : dsc.tmp;
+    const uint32_t ntile = (len + T - 1) / T;
+    const uint32_t lb0 = (uint32_t)(wid * 64 * IPT + lane);
+#pragma unroll 1
+    for (int d = 0; d < D; ++d) {
+      if (sm.flag[d]) continue;  // uniform across the workgroup
+      const int shift = d * BITS;
+      for (int b = tid; b < R; b += THREADS) sm.running[b] = sm.base[d * R + b];
+#pragma unroll 1
+      for (uint32_t t = 0; t < ntile; ++t) {
+        const uint32_t tb = t * (uint32_t)T;
+        uint32_t k[IPT], r[IPT];
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const uint32_t idx = tb + lb0 + j * 64;
+          k[j] = idx < len ? src[idx] : 0xFFFFFFFFu;
+        }
+        seg_rank_tile<BITS, WAVES, IPT, LCOPIES>(sm, k, r, shift);
+        uint32_t* cnt = sm.u.p.cnt + wid * R;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const uint32_t v = (k[j] >> shift) & (R - 1);
+          sm.u.p.stage[cnt[v] + r[j]] = k[j];
+        }
+        __syncthreads();
+        const uint32_t nvalid = (len - tb) < (uint32_t)T ? (len - tb) : (uint32_t)T;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+          const uint32_t i = (uint32_t)(j * THREADS + tid);
+          if (i < nvalid) {
+            const uint32_t key = sm.u.p.stage[i];
+            const uint32_t v = (key >> shift) & (R - 1);
+            dst[sm.running[v] + i - sm.lbase[v]] = key;
+          }
+        }
+        __syncthreads();
+        for (int b = tid; b < R; b += THREADS) sm.running[b] += sm.tot[b];
+      }
+      src = dst;
+      uint32_t* nxt = other;
+      other = dst;
+      dst = nxt;
+      __syncthreads();  // this sweep's writes are complete before the next sweep reads them
+    }
+    if (src != dsc.dst) {  // no sweep ran (copy) or, in place, an odd number ended in tmp
+      for (uint32_t i = tid; i < len; i += THREADS) dsc.dst[i] = src[i];
+    }
+    __syncthreads();
+    seg_splitters<THREADS>(dsc, len);
+  }
+
+  // last workgroup out resets the control block for the next call
+  if (tid == 0) {
+    __threadfence();
+    if (add_agent(&ctl->done2, 1u) == gridDim.x - 1) {
+      __threadfence();
+      for (int c = 0; c < kSegBuckets; ++c) {
+        ctl->count[c] = 0u;
+        ctl->start[c] = 0u;
+        ctl->cursor[c] = 0u;
+      }
+      ctl->nwork = 0u;
+      ctl->head = 0u;
+      ctl->bad = 0u;
+      st_agent(&ctl->done2, 0u);
+    }
+  }
+}
+
+}  // namespace aps

@@ -1,0 +1,36 @@
+// Data structures shared by the segmented-sort kernels and their host callers.
+#pragma once
+
+#include <stdint.h>
+
+namespace aps {
+
+constexpr int kSegBuckets = 32;  // work-list classes: floor(log2(length))
+
+// Control block of the segmented sort (device memory, zero between calls).
+struct SegCtl {
+  uint32_t count[kSegBuckets];   // segments per length class
+  uint32_t start[kSegBuckets];   // first slot of each class in the work order (longest first)
+  uint32_t cursor[kSegBuckets];  // fill cursors
+  uint32_t nwork;                // segments to sort (length >= 2 and valid)
+  uint32_t head;                 // next work item
+  uint32_t done;                 // completion counters for last-workgroup patterns
+  uint32_t done2;
+  uint32_t bad;                  // 1 when some offsets were invalid
+  uint32_t pad[3];
+};
+
+// One unit of work of the persistent sort: sort src[0..n) into dst[0..n) (src == dst allowed),
+// using tmp[0..n) as scratch when more than one tile is needed; when spl is not NULL also write
+// the P-1 splitters of the n sorted keys spread over P cells.
+struct SegDesc {
+  const uint32_t* src;
+  uint32_t* dst;
+  uint32_t* tmp;
+  uint32_t* spl;
+  uint32_t n;
+  uint32_t P;
+  uint32_t pad[2];
+};
+
+}  // namespace aps

@@ -1,0 +1,245 @@
+// HIP executor and C entry points of the sort-request server (ap_server_*).
+//
+// Each slot owns a non-blocking stream, a completion event and a scratch arena carved from the
+// memory budget: [segmented-sort control block][descriptor array][scratch].  A batch of short
+// requests becomes one launch of the persistent segmented kernel over host-built descriptors
+// (longest first), each descriptor pointing at the caller's input and output buffers directly, so
+// no key is copied in or out.  A long request runs alone through the device-wide sort with the
+// arena as its workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "apsort.h"
+#include "apsort_internal.h"
+#include "apsort_seg_types.h"
+#include "apsort_server_core.h"
+
+namespace aps {
+
+static size_t up256s(size_t x) { return (x + 255) / 256 * 256; }
+
+class HipExecutor : public srv::Executor {
+ public:
+  struct SlotRes {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    char* arena = nullptr;
+    SegDesc* h_desc = nullptr;
+    SegCtl* ctl = nullptr;
+    SegDesc* d_desc = nullptr;
+    char* scratch = nullptr;
+  };
+
+  ap_status init(int nslots, size_t budget, int max_batch) {
+    if (hipGetDevice(&dev_) != hipSuccess) return fail(AP_ERR_HIP, "hipGetDevice failed");
+    cfg_ = seg_config();
+    tile_ = (size_t)seg_tile_keys(cfg_);
+    max_batch_ = max_batch;
+    header_ = up256s(sizeof(SegCtl)) + up256s(sizeof(SegDesc) * (size_t)max_batch);
+    const size_t arena = (budget / (size_t)nslots) / 256 * 256;
+    if (arena <= header_ + 256) return fail(AP_ERR_BUDGET, "budget too small for %d slots", nslots);
+    cap_ = arena - header_;
+    slots_.resize(nslots);
+    for (auto& sl : slots_) {
+      hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.arena), arena);
+      if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_desc), sizeof(SegDesc) * max_batch);
+      if (e != hipSuccess) return hip_fail(e, "server slot allocation");
+      sl.ctl = reinterpret_cast<SegCtl*>(sl.arena);
+      sl.d_desc = reinterpret_cast<SegDesc*>(sl.arena + up256s(sizeof(SegCtl)));
+      sl.scratch = sl.arena + header_;
+      ap_status st = fill_u32(reinterpret_cast<uint32_t*>(sl.ctl), 0u, up256s(sizeof(SegCtl)) / 4, sl.stream);
+      if (st != AP_OK) return st;
+    }
+    ap_status st = check_lane_order(slots_[0].stream);
+    if (st != AP_OK) return st;
+    for (auto& sl : slots_) {
+      hipError_t e = hipStreamSynchronize(sl.stream);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return AP_OK;
+  }
+
+  ~HipExecutor() override {
+    for (auto& sl : slots_) {
+      if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+      if (sl.h_desc) (void)hipHostFree(sl.h_desc);
+      if (sl.arena) (void)hipFree(sl.arena);
+      if (sl.ev) (void)hipEventDestroy(sl.ev);
+      if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+  }
+
+  int num_slots() const override { return (int)slots_.size(); }
+  size_t slot_capacity() const override { return cap_; }
+
+  size_t scratch_bytes(const srv::Request& r, bool alone) const override {
+    if (alone) return layout_for(r.n).total;
+    return r.n > tile_ ? up256s(r.n * sizeof(uint32_t)) : 0;  // one-tile requests need no scratch
+  }
+
+  void thread_init() override { (void)hipSetDevice(dev_); }
+
+  ap_status launch_batch(int slot, std::vector<srv::Request*>& reqs) override {
+    SlotRes& sl = slots_[slot];
+    std::sort(reqs.begin(), reqs.end(), [](const srv::Request* a, const srv::Request* b) { return a->n > b->n; });
+    size_t used = 0;
+    uint32_t cnt = 0;
+    for (srv::Request* r : reqs) {
+      SegDesc& d = sl.h_desc[cnt++];
+      d.src = r->in;
+      d.dst = r->out;
+      d.tmp = nullptr;
+      if (r->n > tile_) {
+        d.tmp = reinterpret_cast<uint32_t*>(sl.scratch + used);
+        used += up256s(r->n * sizeof(uint32_t));
+      }
+      d.spl = r->P > 1 ? r->spl : nullptr;
+      d.n = (uint32_t)r->n;
+      d.P = (uint32_t)r->P;
+      d.pad[0] = d.pad[1] = 0u;
+    }
+    hipError_t e = hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(SegDesc) * cnt, hipMemcpyHostToDevice, sl.stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    launch_seg_cfg(cfg_, dim3(seg_workgroups(cfg_, cnt)), sl.stream, sl.d_desc, cnt, sl.ctl);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_seg_sort");
+    e = hipEventRecord(sl.ev, sl.stream);
+    return e == hipSuccess ? AP_OK : hip_fail(e, "hipEventRecord");
+  }
+
+  ap_status launch_alone(int slot, srv::Request* r) override {
+    SlotRes& sl = slots_[slot];
+    const Layout L = layout_for(r->n);
+    ap_status st = AP_OK;
+    if (r->n == 0) {
+      if (r->P > 1 && r->spl) st = fill_u32(r->spl, 0xFFFFFFFFu, (size_t)r->P - 1, sl.stream);
+    } else {
+      st = fill_u32(reinterpret_cast<uint32_t*>(sl.scratch), 0u, L.init_bytes / 4, sl.stream);
+      if (st == AP_OK) st = enqueue_sort(r->in, r->out, r->n, r->P, r->P > 1 ? r->spl : nullptr, sl.scratch, L,
+                                         sl.stream);
+    }
+    if (st != AP_OK) return st;
+    hipError_t e = hipEventRecord(sl.ev, sl.stream);
+    return e == hipSuccess ? AP_OK : hip_fail(e, "hipEventRecord");
+  }
+
+  int query(int slot) override {
+    const hipError_t e = hipEventQuery(slots_[slot].ev);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return -1;
+  }
+
+ private:
+  int dev_ = 0;
+  int cfg_ = 0;
+  size_t tile_ = 8192;
+  int max_batch_ = 256;
+  size_t header_ = 0;
+  size_t cap_ = 0;
+  std::vector<SlotRes> slots_;
+};
+
+}  // namespace aps
+
+struct ap_server {
+  aps::HipExecutor* ex;
+  aps::srv::Server* core;
+};
+
+using namespace aps;
+
+extern "C" {
+
+ap_status ap_server_create(const ap_server_cfg* cfg, ap_server** out) {
+  if (!out) return fail(AP_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  srv::Config c;
+  if (cfg) {
+    if (cfg->hbm_budget_bytes) c.budget = cfg->hbm_budget_bytes;
+    if (cfg->num_streams > 0) c.num_streams = cfg->num_streams;
+    if (cfg->max_batch > 0) c.max_batch = cfg->max_batch;
+    if (cfg->max_queue > 0) c.max_queue = cfg->max_queue;
+    if (cfg->alone_min_keys) c.alone_min_keys = cfg->alone_min_keys;
+  }
+  if (c.num_streams > 64 || c.max_batch > (1 << 20)) return fail(AP_ERR_INVALID, "server configuration out of range");
+  HipExecutor* ex = new HipExecutor();
+  ap_status st = ex->init(c.num_streams, c.budget, c.max_batch);
+  if (st != AP_OK) {
+    delete ex;
+    return st;
+  }
+  ap_server* s = new ap_server{ex, new srv::Server(c, ex)};
+  *out = s;
+  return AP_OK;
+}
+
+ap_status ap_server_submit(ap_server* s, const uint32_t* d_in, uint32_t* d_out, size_t n, int P,
+                           uint32_t* d_splitters, uint64_t* ticket) {
+  if (!s) return fail(AP_ERR_INVALID, "server is NULL");
+  const ap_status st = s->core->submit(d_in, d_out, n, P, d_splitters, 0u, ticket);
+  return st == AP_OK ? st : fail(st, "ap_server_submit rejected the request (status %d)", (int)st);
+}
+
+ap_status ap_server_submit_flags(ap_server* s, const uint32_t* d_in, uint32_t* d_out, size_t n, int P,
+                                 uint32_t* d_splitters, unsigned flags, uint64_t* ticket) {
+  if (!s) return fail(AP_ERR_INVALID, "server is NULL");
+  const ap_status st = s->core->submit(d_in, d_out, n, P, d_splitters, flags, ticket);
+  return st == AP_OK ? st : fail(st, "ap_server_submit rejected the request (status %d)", (int)st);
+}
+
+ap_status ap_server_wait(ap_server* s, uint64_t ticket, int64_t timeout_us) {
+  if (!s) return fail(AP_ERR_INVALID, "server is NULL");
+  return s->core->wait(ticket, timeout_us);
+}
+
+ap_status ap_server_poll(ap_server* s, uint64_t ticket) {
+  if (!s) return fail(AP_ERR_INVALID, "server is NULL");
+  return s->core->poll(ticket);
+}
+
+ap_status ap_server_get_stats(ap_server* s, ap_server_stats* out, int reset_latencies) {
+  if (!s || !out) return fail(AP_ERR_INVALID, "NULL argument");
+  srv::Stats st = s->core->stats();
+  std::memset(out, 0, sizeof *out);
+  out->submitted = st.submitted;
+  out->completed = st.completed;
+  out->failed = st.failed;
+  out->cancelled = st.cancelled;
+  out->batches = st.batches;
+  out->alone = st.alone;
+  out->keys = st.keys;
+  std::vector<double>& v = st.latency_us;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+      const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::max(0.0, p * (double)v.size() - 1.0 + 0.999999));
+      return v[i];
+    };
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->p50_us = pct(0.50);
+    out->p99_us = pct(0.99);
+    out->mean_us = sum / (double)v.size();
+    out->max_us = v.back();
+    out->latency_samples = v.size();
+  }
+  if (reset_latencies) s->core->reset_latencies();
+  return AP_OK;
+}
+
+ap_status ap_server_destroy(ap_server* s) {
+  if (!s) return fail(AP_ERR_INVALID, "server is NULL");
+  s->core->shutdown();
+  delete s->core;
+  delete s->ex;
+  delete s;
+  return AP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+// Scheduling core of the sort-request server: tickets, a bounded arrival queue, admission under a
+// memory budget, continuous batching into per-slot launches, completion and latency statistics.
+//
+// The core knows nothing about HIP: device work goes through the Executor interface (the HIP
+// executor lives in apsort_server.hip).  A slot is one stream with its own scratch arena; at most
+// one batch (or one large request) runs on a slot at a time, so the number of slots bounds the
+// batches in flight and the arenas bound the scratch memory in use.  Requests that arrive while
+// batches run wait in the queue and join the next batch formed on a slot that frees up.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "apsort.h"
+
+namespace aps {
+namespace srv {
+
+inline uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+constexpr unsigned kInjectFault = 1u;  // test hook: the request fails with AP_ERR_DEVICE, alone
+
+struct Request {
+  uint64_t ticket = 0;
+  const uint32_t* in = nullptr;
+  uint32_t* out = nullptr;
+  size_t n = 0;
+  int P = 1;
+  uint32_t* spl = nullptr;
+  unsigned flags = 0;
+  uint64_t t_submit = 0, t_launch = 0, t_done = 0;
+  int status = -1;  // -1 pending/running, else an ap_status
+};
+
+// Device side of the server.  All calls come from the scheduler thread.
+class Executor {
+ public:
+  virtual ~Executor() {}
+  virtual int num_slots() const = 0;
+  // Scratch bytes a request needs on a slot (batched or alone); > slot capacity means it can
+  // never run.
+  virtual size_t scratch_bytes(const Request& r, bool alone) const = 0;
+  virtual size_t slot_capacity() const = 0;
+  // Enqueue the batch on the slot.  Returns AP_OK or an error (then every request of the batch
+  // fails with AP_ERR_DEVICE).
+  virtual ap_status launch_batch(int slot, std::vector<Request*>& reqs) = 0;
+  virtual ap_status launch_alone(int slot, Request* r) = 0;
+  // 1 = the slot's work completed, 0 = still running, < 0 = the device reported an error.
+  virtual int query(int slot) = 0;
+  virtual void thread_init() {}
+};
+
+struct Config {
+  size_t budget = (size_t)64 << 30;
+  int num_streams = 4;
+  int max_batch = 256;
+  int max_queue = 1 << 16;
+  size_t alone_min_keys = (size_t)1 << 20;  // requests at least this long run alone (device-wide)
+};
+
+struct Stats {
+  uint64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, batches = 0, alone = 0, keys = 0;
+  std::vector<double> latency_us;
+};
+
+class Server {
+ public:
+  Server(const Config& cfg, Executor* ex) : cfg_(cfg), ex_(ex) {
+    slots_.resize(ex_->num_slots());
+    worker_ = std::thread([this] { loop(); });
+  }
+
+  ~Server() { shutdown(); }
+
+  // Non-blocking: validates, applies the budget and queue bounds, queues the request.
+  ap_status submit(const uint32_t* in, uint32_t* out, size_t n, int P, uint32_t* spl, unsigned flags,
+                   uint64_t* ticket) {
+    if (!ticket) return AP_ERR_INVALID;
+    if (P < 1 || n >= AP_MAX_KEYS || (n && (!in || !out))) return AP_ERR_INVALID;
+    if (n && in != out) {
+      const uintptr_t a0 = (uintptr_t)in, a1 = a0 + n * 4, b0 = (uintptr_t)out, b1 = b0 + n * 4;
+      if (a0 < b1 && b0 < a1) return AP_ERR_INVALID;
+    }
+    Request* r = new Request();
+    r->in = in;
+    r->out = out;
+    r->n = n;
+    r->P = P;
+    r->spl = spl;
+    r->flags = flags;
+    const bool alone = n >= cfg_.alone_min_keys;
+    if (ex_->scratch_bytes(*r, alone) > ex_->slot_capacity()) {
+      delete r;
+      return AP_ERR_BUDGET;
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    if (stopping_) {
+      delete r;
+      return AP_ERR_CANCELLED;
+    }
+    if ((int)pending_.size() >= cfg_.max_queue) {
+      delete r;
+      return AP_ERR_QUEUE_FULL;
+    }
+    r->ticket = ++next_ticket_;
+    r->t_submit = now_ns();
+    tickets_[r->ticket] = r;
+    pending_.push_back(r);
+    stats_.submitted++;
+    *ticket = r->ticket;
+    cv_work_.notify_one();
+    return AP_OK;
+  }
+
+  // Final status of the ticket, or AP_ERR_TIMEOUT when it is not done within timeout_us
+  // (< 0: wait forever).  A ticket whose final status was returned is forgotten.
+  ap_status wait(uint64_t ticket, int64_t timeout_us) {
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = tickets_.find(ticket);
+    if (it == tickets_.end()) return AP_ERR_INVALID;
+    Request* r = it->second;
+    auto done = [&] { return r->status >= 0; };
+    if (timeout_us < 0) {
+      cv_done_.wait(lk, done);
+    } else if (!cv_done_.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+      return AP_ERR_TIMEOUT;
+    }
+    const ap_status st = (ap_status)r->status;
+    tickets_.erase(it);
+    delete r;
+    return st;
+  }
+
+  ap_status poll(uint64_t ticket) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = tickets_.find(ticket);
+    if (it == tickets_.end()) return AP_ERR_INVALID;
+    Request* r = it->second;
+    if (r->status < 0) return AP_ERR_TIMEOUT;
+    const ap_status st = (ap_status)r->status;
+    tickets_.erase(it);
+    delete r;
+    return st;
+  }
+
+  Stats stats() {
+    std::lock_guard<std::mutex> lk(mu_);
+    return stats_;
+  }
+
+  void reset_latencies() {
+    std::lock_guard<std::mutex> lk(mu_);
+    stats_.latency_us.clear();
+  }
+
+  // Stop accepting, cancel queued requests, let in-flight work finish, join the scheduler.
+  void shutdown() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (joined_) return;
+      stopping_ = true;
+      for (Request* r : pending_) {
+        r->status = AP_ERR_CANCELLED;
+        r->t_done = now_ns();
+        stats_.cancelled++;
+      }
+      pending_.clear();
+      cv_work_.notify_all();
+      cv_done_.notify_all();
+    }
+    worker_.join();
+    std::lock_guard<std::mutex> lk(mu_);
+    joined_ = true;
+    for (auto& kv : tickets_) delete kv.second;
+    tickets_.clear();
+  }
+
+ private:
+  struct Slot {
+    bool busy = false;
+    std::vector<Request*> reqs;
+  };
+
+  void finish(Request* r, ap_status st, uint64_t t) {
+    r->status = st;
+    r->t_done = t;
+    if (st == AP_OK) {
+      stats_.completed++;
+      stats_.keys += r->n;
+      stats_.latency_us.push_back((double)(t - r->t_submit) / 1e3);
+    } else {
+      stats_.failed++;
+    }
+  }
+
+  // Takes the next unit of work from the queue head (FIFO): a long request alone, or a batch of
+  // the queued requests that are not long, in arrival order, up to max_batch and the slot's scratch
+  // capacity.  Long requests behind the head wait for their turn; short ones may overtake them.
+  bool form_work(std::vector<Request*>& batch, bool& alone) {
+    batch.clear();
+    if (pending_.empty()) return false;
+    Request* head = pending_.front();
+    if (head->n >= cfg_.alone_min_keys) {
+      pending_.pop_front();
+      batch.push_back(head);
+      alone = true;
+      return true;
+    }
+    alone = false;
+    size_t used = 0;
+    const size_t cap = ex_->slot_capacity();
+    for (auto it = pending_.begin(); it != pending_.end() && (int)batch.size() < cfg_.max_batch;) {
+      Request* r = *it;
+      if (r->n >= cfg_.alone_min_keys) {
+        ++it;
+        continue;
+      }
+      const size_t need = ex_->scratch_bytes(*r, false);
+      if (used + need > cap) break;
+      used += need;
+      batch.push_back(r);
+      it = pending_.erase(it);
+    }
+    return !batch.empty();
+  }
+
+  void loop() {
+    ex_->thread_init();
+    std::vector<Request*> batch;
+    std::unique_lock<std::mutex> lk(mu_);
+    while (true) {
+      // completions
+      bool any_busy = false;
+      for (int s = 0; s < (int)slots_.size(); ++s) {
+        Slot& sl = slots_[s];
+        if (!sl.busy) continue;
+        lk.unlock();
+        const int q = ex_->query(s);
+        lk.lock();
+        if (q == 0) {
+          any_busy = true;
+          continue;
+        }
+        const uint64_t t = now_ns();
+        for (Request* r : sl.reqs) finish(r, q > 0 ? AP_OK : AP_ERR_DEVICE, t);
+        sl.reqs.clear();
+        sl.busy = false;
+        cv_done_.notify_all();
+      }
+      // launches on free slots
+      for (int s = 0; s < (int)slots_.size(); ++s) {
+        if (slots_[s].busy) continue;
+        bool alone = false;
+        if (!form_work(batch, alone)) break;
+        const uint64_t t = now_ns();
+        // test hook: requests flagged for an injected fault fail on their own, without running
+        for (auto it = batch.begin(); it != batch.end();) {
+          if ((*it)->flags & kInjectFault) {
+            finish(*it, AP_ERR_DEVICE, t);
+            it = batch.erase(it);
+          } else {
+            ++it;
+          }
+        }
+        if (batch.empty()) {
+          cv_done_.notify_all();
+          --s;  // the slot is still free
+          continue;
+        }
+        for (Request* r : batch) r->t_launch = t;
+        lk.unlock();
+        const ap_status st = alone ? ex_->launch_alone(s, batch[0]) : ex_->launch_batch(s, batch);
+        lk.lock();
+        if (alone) stats_.alone++;
+        else stats_.batches++;
+        if (st != AP_OK) {
+          const uint64_t t2 = now_ns();
+          for (Request* r : batch)
+            if (r->status < 0) finish(r, AP_ERR_DEVICE, t2);
+          cv_done_.notify_all();
+          continue;
+        }
+        slots_[s].busy = true;
+        slots_[s].reqs = batch;
+        any_busy = true;
+      }
+      bool idle = true;
+      for (auto& sl : slots_) idle = idle && !sl.busy;
+      if (stopping_ && pending_.empty() && idle) break;
+      if (any_busy) {
+        // device work in flight: poll again shortly, or earlier if a request arrives
+        cv_work_.wait_for(lk, std::chrono::microseconds(20));
+      } else if (pending_.empty()) {
+        cv_work_.wait(lk, [&] { return stopping_ || !pending_.empty(); });
+      }
+    }
+  }
+
+  Config cfg_;
+  Executor* ex_;
+  std::mutex mu_;
+  std::condition_variable cv_work_, cv_done_;
+  std::deque<Request*> pending_;
+  std::unordered_map<uint64_t, Request*> tickets_;
+  std::vector<Slot> slots_;
+  Stats stats_;
+  uint64_t next_ticket_ = 0;
+  bool stopping_ = false;
+  bool joined_ = false;
+  std::thread worker_;
+};
+
+}  // namespace srv
+}  // namespace aps

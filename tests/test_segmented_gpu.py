@@ -1,0 +1,139 @@
+"""Parity of the batched segmented sort (A8) with the CPU oracle, through the C ABI."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0004013_amd import inputs
+from tests.gpu_util import announce, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(keys: np.ndarray, offsets: np.ndarray, cfg: int | None = None, pad_front: int = 0):
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    t_keys, _ = to_dev(keys, pad_front)
+    t_off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.uint32).view(np.int32)).to("cuda")
+    t_st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    if cfg is not None:
+        binding.ap_segmented_set_config(cfg)
+    try:
+        binding.ap_sort_u32_segmented(t_keys, t_off, t_st)
+        torch.cuda.synchronize()
+    finally:
+        if cfg is not None:
+            binding.ap_segmented_set_config(0)
+    return to_host(t_keys), int(to_host(t_st)[0])
+
+
+def _check(keys, offsets, **kw):
+    announce(f"segmented nseg={len(offsets) - 1} n={keys.size} {kw}")
+    got, status = _run(keys, offsets, **kw)
+    want = oracle.sort_segmented(keys, offsets.astype(np.uint64))
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+    assert status == 0
+    return got
+
+
+def _batch(lengths, seed=0):
+    L = np.asarray(lengths, dtype=np.int64)
+    keys, off, _ = inputs.segment_keys(L)
+    return keys, off
+
+
+def test_log_uniform_batch_512():
+    """512 segments, lengths log-uniform in [64, 2^18], distributions (a)-(e) by segment seed."""
+    L = inputs.segment_lengths(512, seed=0)
+    keys, off = _batch(L)
+    _check(keys, off)
+
+
+@pytest.mark.parametrize("cfg", range(7))
+def test_every_config(cfg):
+    L = inputs.segment_lengths(96, seed=cfg + 1, lo=2, hi=1 << 16)
+    L[::7] = 0
+    L[::11] = 1
+    keys, off = _batch(L)
+    _check(keys, off, cfg=cfg)
+
+
+def test_boundary_lengths():
+    """Lengths at every tile-size boundary +-1 and a few multi-tile sizes."""
+    Ls = []
+    for T in (1024, 2048, 4096, 8192, 16384):
+        Ls += [T - 1, T, T + 1]
+    Ls += [0, 1, 2, 3, 63, 64, 65, 3 * 8192 + 5, 100_000, 1 << 18]
+    keys, off = _batch(Ls)
+    _check(keys, off)
+
+
+def test_single_large_segment():
+    keys, off = _batch([(1 << 20) + 3])
+    _check(keys, off)
+
+
+def test_constant_and_clustered_segments():
+    rng = np.random.default_rng(3)
+    parts, L = [], []
+    for i, n in enumerate([70_000, 5000, 40_000, 9000]):
+        if i % 2 == 0:
+            parts.append(np.full(n, 123456 + i, np.uint32))
+        else:
+            parts.append((rng.integers(0, 4, n).astype(np.uint32) << np.uint32(24)) | np.uint32(77))
+        L.append(n)
+    keys = np.concatenate(parts)
+    off = np.zeros(len(L) + 1, np.int64)
+    np.cumsum(L, out=off[1:])
+    _check(keys, off.astype(np.uint32))
+
+
+def test_full_range_keys_and_unaligned_segments():
+    rng = np.random.default_rng(9)
+    keys = rng.integers(0, 1 << 32, size=300_001, dtype=np.uint64).astype(np.uint32)
+    cuts = np.sort(rng.choice(np.arange(1, keys.size), size=40, replace=False))
+    off = np.concatenate([[3], cuts, [keys.size - 2]]).astype(np.uint32)   # keys outside stay put
+    got = _check(keys, off, pad_front=1)
+    assert np.array_equal(got[:3], keys[:3]) and np.array_equal(got[-2:], keys[-2:])
+
+
+def test_invalid_offsets_reported():
+    keys, off = _batch([1000, 2000, 3000])
+    bad = off.copy()
+    bad[2] = bad[1] - 10                 # segment 1 decreasing
+    got, status = _run(keys, bad)
+    assert status == 1                   # AP_ERR_INVALID
+    assert np.array_equal(got[:1000], np.sort(keys[:1000]))
+
+
+def test_graph_replay_and_recapture():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    L = inputs.segment_lengths(64, seed=5)
+    keys, off = _batch(L)
+    want = oracle.sort_segmented(keys, off.astype(np.uint64))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t_off = torch.from_numpy(off.view(np.int32)).to("cuda")
+        t_keys, _ = to_dev(keys)
+        for rep in range(4):             # first call captures, the rest replay
+            t_keys.copy_(torch.from_numpy(keys.view(np.int32)).to("cuda"))
+            binding.ap_sort_u32_segmented(t_keys, t_off)
+            s.synchronize()
+            assert np.array_equal(to_host(t_keys), want), rep
+        keys2, off2 = _batch(inputs.segment_lengths(33, seed=6))
+        t2, _ = to_dev(keys2)
+        t_off2 = torch.from_numpy(off2.view(np.int32)).to("cuda")
+        binding.ap_sort_u32_segmented(t2, t_off2)
+        s.synchronize()
+        assert np.array_equal(to_host(t2), oracle.sort_segmented(keys2, off2.astype(np.uint64)))
+
+
+def test_empty_batch():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    t = torch.zeros(4, dtype=torch.int32, device="cuda")
+    binding.ap_sort_u32_segmented(t, torch.zeros(1, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()

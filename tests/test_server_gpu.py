@@ -1,0 +1,175 @@
+"""Served form (A9): requests submitted to the ap_server_* request loop are sorted exactly like the
+oracle, alone and inside a mix; admission, fault isolation and cancellation behave as specified."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0004013_amd import inputs
+from tests.gpu_util import announce, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+AP_OK, AP_ERR_BUDGET, AP_ERR_TIMEOUT, AP_ERR_DEVICE, AP_ERR_CANCELLED = 0, 4, 6, 7, 8
+
+
+class Pool:
+    """Five device-resident key pools (one per distribution); requests are windows into them."""
+
+    def __init__(self, keys_per_pool: int):
+        torch = torch_cuda()
+        self.host = {d: inputs.keyset(d, keys_per_pool, seed=100 + i).keys for i, d in enumerate(inputs.DISTS)}
+        self.dev = {d: torch.from_numpy(k.view(np.int32)).to("cuda") for d, k in self.host.items()}
+        self.size = keys_per_pool
+
+
+def _requests(pool: Pool, nreq: int, lo: int, hi: int, seed: int = 0):
+    tr = inputs.request_trace(nreq, rate_per_s=1e6, pool_keys=pool.size, seed=seed, lo=lo, hi=hi)
+    return tr
+
+
+def _run(server, pool, reqs, P=64, gap_s=0.0):
+    torch = torch_cuda()
+    outs, spls, tickets = [], [], []
+    for r in reqs:
+        src = pool.dev[r.dist][r.pool_offset:r.pool_offset + r.n]
+        out = torch.empty(r.n, dtype=torch.int32, device="cuda")
+        spl = torch.empty(P - 1, dtype=torch.int32, device="cuda")
+        outs.append(out)
+        spls.append(spl)
+        tickets.append(server.submit(src, out, P, spl))
+        if gap_s:
+            time.sleep(gap_s)
+    statuses = [server.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    return statuses, [to_host(o) for o in outs], [to_host(s) for s in spls]
+
+
+def _want(pool, r, P=64):
+    w = oracle.sort_u32(pool.host[r.dist][r.pool_offset:r.pool_offset + r.n])
+    return w, oracle.splitters(w, P)
+
+
+def test_mixed_sizes_match_oracle():
+    from paper_cs_0004013_amd import binding
+    pool = Pool(1 << 21)
+    reqs = _requests(pool, 160, 1 << 4, 1 << 20, seed=1)
+    announce("server mixed 160 requests")
+    with binding.Server(hbm_budget_bytes=1 << 30, num_streams=4, max_batch=64, alone_min_keys=1 << 18) as srv:
+        st, outs, spls = _run(srv, pool, reqs)
+        stats = srv.stats()
+    assert all(s == AP_OK for s in st)
+    for r, o, sp in zip(reqs, outs, spls):
+        w, ws = _want(pool, r)
+        assert np.array_equal(o, w) and np.array_equal(sp, ws), r
+    assert stats["completed"] == len(reqs)
+    assert stats["batches"] < len(reqs)          # short requests were batched
+    assert stats["alone"] >= 1                   # long ones ran device-wide
+
+
+def test_alone_vs_mix_identical():
+    """Each request gives byte-identical output run alone and inside a Poisson mix."""
+    from paper_cs_0004013_amd import binding
+    pool = Pool(1 << 20)
+    reqs = _requests(pool, 48, 1 << 10, 1 << 19, seed=2)
+    announce("server alone vs mix")
+    with binding.Server(hbm_budget_bytes=1 << 29, num_streams=3, max_batch=32, alone_min_keys=1 << 18) as srv:
+        alone = []
+        for r in reqs:                            # one at a time: each runs alone
+            st, o, sp = _run(srv, pool, [r])
+            assert st == [AP_OK]
+            alone.append((o[0], sp[0]))
+        rng = np.random.default_rng(0)
+        order = rng.permutation(len(reqs))
+        torch = torch_cuda()
+        outs, spls, tks = {}, {}, {}
+        for i in order:                           # the mix: exponential gaps, arrivals during runs
+            r = reqs[i]
+            src = pool.dev[r.dist][r.pool_offset:r.pool_offset + r.n]
+            outs[i] = torch.empty(r.n, dtype=torch.int32, device="cuda")
+            spls[i] = torch.empty(63, dtype=torch.int32, device="cuda")
+            tks[i] = srv.submit(src, outs[i], 64, spls[i])
+            time.sleep(float(rng.exponential(20e-6)))
+        assert all(srv.wait(tks[i]) == AP_OK for i in order)
+        torch.cuda.synchronize()
+    for i, r in enumerate(reqs):
+        w, ws = _want(pool, r)
+        assert np.array_equal(to_host(outs[i]), alone[i][0]) and np.array_equal(alone[i][0], w)
+        assert np.array_equal(to_host(spls[i]), alone[i][1]) and np.array_equal(alone[i][1], ws)
+
+
+def test_admission_under_tiny_budget():
+    from paper_cs_0004013_amd import binding
+    torch = torch_cuda()
+    pool = Pool(1 << 20)
+    with binding.Server(hbm_budget_bytes=8 << 20, num_streams=2, max_batch=16, alone_min_keys=1 << 30) as srv:
+        big = pool.dev["a"][:1 << 20]
+        out = torch.empty_like(big)
+        st, _ = srv.try_submit_ptr(big.data_ptr(), out.data_ptr(), 1 << 20, 1)  # 4 MiB scratch > 4 MiB slot
+        assert st == AP_ERR_BUDGET
+        reqs = _requests(pool, 40, 1 << 16, 1 << 19, seed=3)   # each fits, together they exceed the budget
+        st, outs, spls = _run(srv, pool, reqs)
+        assert all(s == AP_OK for s in st)
+        for r, o, sp in zip(reqs, outs, spls):
+            w, ws = _want(pool, r)
+            assert np.array_equal(o, w) and np.array_equal(sp, ws)
+
+
+def test_injected_fault_fails_only_its_ticket():
+    from paper_cs_0004013_amd import binding
+    torch = torch_cuda()
+    pool = Pool(1 << 18)
+    with binding.Server(hbm_budget_bytes=1 << 28, num_streams=2) as srv:
+        tk, outs = [], []
+        for i in range(12):
+            src = pool.dev["d"][i * 1000:(i + 1) * 1000]
+            out = torch.empty(1000, dtype=torch.int32, device="cuda")
+            outs.append(out)
+            tk.append(srv.submit_ptr(src.data_ptr(), out.data_ptr(), 1000, 1, None,
+                                     binding.AP_SUBMIT_INJECT_FAULT if i == 5 else 0))
+        st = [srv.wait(t) for t in tk]
+        torch.cuda.synchronize()
+    assert st[5] == AP_ERR_DEVICE and all(s == AP_OK for i, s in enumerate(st) if i != 5)
+    for i in range(12):
+        if i != 5:
+            assert np.array_equal(to_host(outs[i]), np.sort(pool.host["d"][i * 1000:(i + 1) * 1000]))
+
+
+def test_edge_requests_in_place_empty_tiny():
+    from paper_cs_0004013_amd import binding
+    torch = torch_cuda()
+    with binding.Server(hbm_budget_bytes=1 << 28, num_streams=2, alone_min_keys=1 << 16) as srv:
+        rng = np.random.default_rng(4)
+        cases = []
+        for n in (0, 1, 2, 5, 8191, 8192, 8193, 70_000, (1 << 16) + 3):
+            keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+            t = torch.from_numpy(keys.view(np.int32)).to("cuda") if n else torch.empty(0, dtype=torch.int32,
+                                                                                       device="cuda")
+            spl = torch.empty(99, dtype=torch.int32, device="cuda")
+            tk = srv.submit_ptr(t.data_ptr() if n else 0, t.data_ptr() if n else 0, n, 100, spl.data_ptr())
+            cases.append((keys, t, spl, tk))
+        for keys, t, spl, tk in cases:
+            assert srv.wait(tk) == AP_OK
+        torch.cuda.synchronize()
+        for keys, t, spl, tk in cases:
+            w = oracle.sort_u32(keys)
+            assert np.array_equal(to_host(t) if keys.size else keys, w)
+            assert np.array_equal(to_host(spl), oracle.splitters(w, 100))
+
+
+def test_destroy_cancels_queued():
+    from paper_cs_0004013_amd import binding
+    torch = torch_cuda()
+    pool = Pool(1 << 22)
+    srv = binding.Server(hbm_budget_bytes=1 << 30, num_streams=1, alone_min_keys=1 << 20)
+    outs = []
+    for i in range(6):
+        src = pool.dev["a"][:1 << 22]
+        out = torch.empty(1 << 22, dtype=torch.int32, device="cuda")
+        outs.append(out)
+        srv.submit(src, out, 64)
+    srv.close()                                   # running one finishes, queued ones are cancelled
+    torch.cuda.synchronize()
