@@ -1,15 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark of the radix sort on one MI355X.
+"""Benchmark of the radix sort on one MI355X.  Prints ONE JSON line.
 
-A step is one full sort (bucket counts + plan, every digit pass, splitters) of 2^26 uint32 keys,
-i.i.d. uniform in [0, 2^31-1] (distribution (a), seed 1), already resident in HBM, into P = 64 cells.
-`value` is keys sorted per second over the K timed steps (Gkeys/s).  The roofline object describes
-the digit-pass kernel (k_pass), timed with HIP events recorded around each launch on the sort's
-stream during the timed steps.  The other distributions (b)-(e) at 2^26 and the adversarial 2^27
-set are reported as extra fields.  The CPU baseline is the oracle (plain single-threaded C LSD
-radix sort) on the same 2^26-key array.
+Main metric: a step is one full sort (bucket counts + plan, every digit pass, splitters) of 2^26
+uint32 keys, i.i.d. uniform in [0, 2^31-1] (distribution (a), seed 1), already resident in HBM,
+into P = 64 cells; `value` is keys sorted per second over the K timed steps (Gkeys/s).
 
-Prints ONE JSON line.
+`roofline` describes the digit-pass kernel k_pass: algorithmic bytes per launch (8 B per key) over
+the mean launch duration, timed with HIP events recorded around each launch on the sort's stream
+during the timed steps.  `traffic` comes from the committed rocprofv3 counter summary when it was
+taken on the current kernel source.
+
+Extra fields (each can be skipped): the other distributions (b)-(e) at 2^26 and the adversarial
+2^27 set; the 4096-segment batch (lengths log-uniform in [64, 2^18]) sorted by the batched
+segmented form vs a loop of plain per-array launches; the served form (Poisson arrivals of
+log-uniform [2^10, 2^24] requests at several rates) vs one plain launch per request, FIFO on one
+stream; p50/p99 latency of a 2^20-key sort.  The CPU baseline is the oracle (plain
+single-threaded C LSD radix sort) on the same 2^26 keys.
 """
 from __future__ import annotations
 
@@ -76,13 +82,182 @@ def time_sorts(binding, torch, t_in, t_out, spl, steps: int, warmup: int, profil
     return dt, prof
 
 
+def pct(v, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), p)) if len(v) else None
+
+
+# ------------------------------------------------------------------------------------------------
+def leg_latency(binding, torch, np, inputs):
+    """2^20 uniform keys (seed 0), 64 cells: per-sort latency over 50 timed sorts."""
+    keys = inputs.keyset("a", 1 << 20, seed=0).keys
+    t_in = torch.from_numpy(keys.view(np.int32)).to("cuda")
+    t_out = torch.empty_like(t_in)
+    spl = torch.empty(63, dtype=torch.int32, device="cuda")
+    ms = []
+    for i in range(55):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        binding.ap_sort_u32(t_in, t_out, 64, spl)
+        b.record()
+        torch.cuda.synchronize()
+        if i >= 5:
+            ms.append(a.elapsed_time(b))
+    return {"n": 1 << 20, "p50_ms": round(pct(ms, 50), 4), "p99_ms": round(pct(ms, 99), 4),
+            "gkeys_s_p50": round((1 << 20) / pct(ms, 50) / 1e6, 2)}
+
+
+def leg_segmented(binding, torch, np, inputs, steps: int):
+    """4096 segments, lengths log-uniform in [64, 2^18] (seed 0); segment s uses seed s."""
+    L = inputs.segment_lengths(4096, seed=0)
+    keys, off, _ = inputs.segment_keys(L)
+    n = int(keys.size)
+    s = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(s):
+        t_src = torch.from_numpy(keys.view(np.int32)).to("cuda")
+        t_work = torch.empty_like(t_src)
+        t_off = torch.from_numpy(off.view(np.int32)).to("cuda")
+        ms = []
+        for i in range(steps + 2):
+            t_work.copy_(t_src)              # restore the unsorted input (outside the timed region)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            binding.ap_sort_u32_segmented(t_work, t_off, stream=s)
+            b.record(s)
+            s.synchronize()
+            if i >= 2:
+                ms.append(a.elapsed_time(b))
+        got = t_work.cpu().numpy().view(np.uint32)
+        # cheap full check: nondecreasing inside every segment, multiset kept per segment boundary
+        d = np.diff(got.astype(np.int64))
+        inside = np.ones(n - 1, dtype=bool)
+        inside[off[1:-1].astype(np.int64) - 1] = False
+        ok = bool(np.all(d[inside] >= 0)) and int(got.astype(np.uint64).sum()) == int(keys.astype(np.uint64).sum())
+        res["segments"] = 4096
+        res["keys"] = n
+        res["batched_ms_p50"] = round(pct(ms, 50), 4)
+        res["batched_gkeys_s"] = round(n / pct(ms, 50) / 1e6, 3)
+        res["batched_ok"] = ok
+        # baseline: one plain ap_sort_u32 per segment, in order, on the same stream
+        lib = binding.lib()
+        base_ptr = t_work.data_ptr()
+        offs = off.astype(np.int64)
+        sid = s.cuda_stream
+        ms_b = []
+        for i in range(2):
+            t_work.copy_(t_src)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            for k in range(4096):
+                p = base_ptr + 4 * int(offs[k])
+                st = lib.ap_sort_u32(p, p, int(offs[k + 1] - offs[k]), 1, None, sid)
+                if st:
+                    raise RuntimeError(f"ap_sort_u32 failed: {binding.last_error()}")
+            b.record(s)
+            s.synchronize()
+            ms_b.append(a.elapsed_time(b))
+        res["loop_of_plain_launches_ms"] = round(min(ms_b), 3)
+        res["loop_of_plain_launches_gkeys_s"] = round(n / min(ms_b) / 1e6, 3)
+        res["speedup_vs_loop"] = round(min(ms_b) / pct(ms, 50), 2)
+    return res
+
+
+def leg_served(binding, torch, np, inputs, pools_dev, nreq: int, rates):
+    """Poisson trace of nreq requests (sizes log-uniform [2^10, 2^24], distribution and pool
+    window by request seed) served by the request server at several offered rates, and the same
+    trace as one plain launch per request, FIFO on one stream."""
+    pool_keys = int(next(iter(pools_dev.values())).numel())
+    ring = 128                                 # output buffers reused round-robin
+    outs = [torch.empty(1 << 24, dtype=torch.int32, device="cuda") for _ in range(ring)]
+    spls = [torch.empty(63, dtype=torch.int32, device="cuda") for _ in range(ring)]
+    lib = binding.lib()
+    res = {"requests": nreq, "pool_keys": pool_keys}
+
+    # -- baseline: plain launches back to back (closed loop) gives the capacity, then its latency
+    base_trace = inputs.request_trace(nreq, rate_per_s=1.0, pool_keys=pool_keys, seed=0)
+    total_keys = sum(r.n for r in base_trace)
+    s = torch.cuda.Stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nreq)]
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(s)
+    t0 = time.perf_counter()
+    for i, r in enumerate(base_trace):
+        src = pools_dev[r.dist][r.pool_offset:r.pool_offset + r.n]
+        st = lib.ap_sort_u32(src.data_ptr(), outs[i % ring].data_ptr(), r.n, 64, spls[i % ring].data_ptr(),
+                             s.cuda_stream)
+        if st:
+            raise RuntimeError(binding.last_error())
+        evs[i].record(s)
+    s.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_cap = nreq / t_plain
+    res["plain_fifo_closed_loop"] = {"req_s": round(plain_cap, 1), "gkeys_s": round(total_keys / t_plain / 1e9, 3)}
+
+    # -- served, open loop at rates relative to the plain capacity; plain FIFO at the same rates
+    res["points"] = []
+    with binding.Server(hbm_budget_bytes=64 << 30, num_streams=4, max_batch=256, alone_min_keys=1 << 20) as srv:
+        for frac in rates:
+            lam = frac * plain_cap
+            tr = inputs.request_trace(nreq, rate_per_s=lam, pool_keys=pool_keys, seed=0)
+            srv.stats(reset_latencies=True)
+            tickets = [0] * nreq
+            t0 = time.perf_counter()
+            for i, r in enumerate(tr):
+                while time.perf_counter() - t0 < r.arrival_s:
+                    pass
+                if i >= ring:
+                    st = srv.wait(tickets[i - ring])  # output buffer reuse
+                    if st:
+                        raise RuntimeError(f"request failed: {st}")
+                src = pools_dev[r.dist][r.pool_offset:r.pool_offset + r.n]
+                tickets[i] = srv.submit_ptr(src.data_ptr(), outs[i % ring].data_ptr(), r.n, 64,
+                                            spls[i % ring].data_ptr())
+            for i in range(max(0, nreq - ring), nreq):
+                st = srv.wait(tickets[i])
+                if st:
+                    raise RuntimeError(f"request failed: {st}")
+            wall = time.perf_counter() - t0
+            stt = srv.stats(reset_latencies=True)
+            # plain FIFO at the same offered rate: latency = completion event - arrival
+            start = torch.cuda.Event(enable_timing=True)
+            t1 = time.perf_counter()
+            start.record(s)
+            for i, r in enumerate(tr):
+                while time.perf_counter() - t1 < r.arrival_s:
+                    pass
+                src = pools_dev[r.dist][r.pool_offset:r.pool_offset + r.n]
+                lib.ap_sort_u32(src.data_ptr(), outs[i % ring].data_ptr(), r.n, 64, spls[i % ring].data_ptr(),
+                                s.cuda_stream)
+                evs[i].record(s)
+            s.synchronize()
+            wall_p = time.perf_counter() - t1
+            lat_p = [start.elapsed_time(evs[i]) - tr[i].arrival_s * 1e3 for i in range(nreq)]
+            res["points"].append({
+                "offered_frac_of_plain_capacity": frac,
+                "offered_req_s": round(lam, 1),
+                "served": {"gkeys_s": round(sum(r.n for r in tr) / wall / 1e9, 3), "p50_ms": round(stt["p50_us"] / 1e3, 4),
+                           "p99_ms": round(stt["p99_us"] / 1e3, 4), "batches": stt["batches"], "alone": stt["alone"]},
+                "plain_fifo": {"gkeys_s": round(sum(r.n for r in tr) / wall_p / 1e9, 3),
+                               "p50_ms": round(pct(lat_p, 50), 4), "p99_ms": round(pct(lat_p, 99), 4)},
+            })
+            log(f"served frac={frac}: {res['points'][-1]}")
+    return res
+
+
+# ------------------------------------------------------------------------------------------------
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the other distributions")
+    ap.add_argument("--no-extra", action="store_true", help="skip every extra leg")
+    ap.add_argument("--no-dists", action="store_true", help="skip distributions (b)-(e) and the 2^27 set")
+    ap.add_argument("--no-segmented", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=20000)
+    ap.add_argument("--served-rates", default="0.5,0.9,1.25")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -138,20 +313,32 @@ def main() -> int:
     }
 
     extra = {}
-    if not args.no_extra:
+    pools = {"a": t_in}
+    if not args.no_extra and not args.no_dists:
         for seed, dist in zip(range(2, 6), "bcde"):
             log(f"distribution ({dist}) seed {seed}")
             k2 = upload(inputs.keyset(dist, N_MAIN, seed=seed).keys)
             o2 = torch.empty_like(k2)
             d2, _ = time_sorts(binding, torch, k2, o2, spl, 10, 3, False)
             extra[f"dist_{dist}_gkeys_s"] = round(N_MAIN * 10 / d2 / 1e9, 3)
-            del k2, o2
+            pools[dist] = k2
+            del o2
         log("adversarial 2^27")
         k3 = upload(inputs.adversarial(1 << 27, seed=0).keys)
         o3 = torch.empty_like(k3)
-        d3, (ms3, l3) = time_sorts(binding, torch, k3, o3, spl, 5, 2, True)
+        d3, _ = time_sorts(binding, torch, k3, o3, spl, 5, 2, False)
         extra["adversarial_2p27_gkeys_s"] = round((1 << 27) * 5 / d3 / 1e9, 3)
         del k3, o3
+    if not args.no_extra:
+        log("latency 2^20")
+        extra["latency_2p20"] = leg_latency(binding, torch, np, inputs)
+    if not args.no_extra and not args.no_segmented:
+        log("segmented 4096-segment batch")
+        extra["segmented_4096"] = leg_segmented(binding, torch, np, inputs, steps=5)
+    if not args.no_extra and not args.no_served and len(pools) == 5:
+        log("served form")
+        rates = [float(x) for x in args.served_rates.split(",") if x]
+        extra["served"] = leg_served(binding, torch, np, inputs, pools, args.served_requests, rates)
 
     cpu = None
     if not args.no_cpu:

@@ -132,10 +132,10 @@ ap_status ap_digit_plan_u32(const uint32_t *d_in, size_t n, int digit_bits,
  *   d_offsets  nseg + 1 uint32_t offsets (device), nondecreasing.
  *   nseg       number of segments, >= 0.
  *   d_status   optional device uint32_t: set to 0 when the offsets are valid,
- *              to AP_ERR_INVALID when some segment has a decreasing or
- *              out-of-range offset (such segments are left unsorted).  The
- *              offsets live on the device, so this check completes with the
- *              stream work rather than at the call.
+ *              to AP_ERR_INVALID when some offset decreases or exceeds n_total;
+ *              then no segment is sorted (invalid offsets make segments
+ *              overlap).  The offsets live on the device, so this check
+ *              completes with the stream work rather than at the call.
  *
  * One workgroup sorts each segment: segments that fit one tile are sorted in
  * registers and LDS (one read and one write of each key); longer ones by the
@@ -153,13 +153,25 @@ ap_status ap_sort_u32_segmented(uint32_t *d_keys, size_t n_total,
 size_t ap_segmented_workspace_bytes(size_t n_total, int nseg);
 
 /*
- * Segmented-sort kernel configuration (digit width, waves per workgroup, keys
- * per lane), chosen by the tuner: ap_segmented_num_configs() configurations
- * are compiled in; ap_segmented_set_config(i) selects one for later calls
- * (process-wide; index 0 is the default).
+ * Segmented-sort tuning.  Segments (and batched server requests) fall in
+ * length groups: group g covers the lengths whose floor(log2(length)) lies in
+ * [cls_lo, cls_hi] and runs kernel configuration cfg (digit width, waves per
+ * workgroup, keys per lane; ap_segmented_num_configs() configurations are
+ * compiled in, see ap_segmented_config_info).  The groups must not overlap;
+ * a group with cls_lo > cls_hi is unused.  Settings are process-wide.
+ *   ap_segmented_set_config(cfg)  every group uses cfg
+ *   ap_segmented_set_group / ap_segmented_get_group  one group
+ *   ap_load_tuning(path)  replace the table from a text file with lines
+ *                         "group cls_lo cls_hi cfg" ('#' starts a comment),
+ *                         as written by the package's autotuner
  */
 int ap_segmented_num_configs(void);
+ap_status ap_segmented_config_info(int cfg, int *digit_bits, int *waves,
+                                   int *keys_per_lane);
 ap_status ap_segmented_set_config(int cfg);
+ap_status ap_segmented_set_group(int g, int cls_lo, int cls_hi, int cfg);
+ap_status ap_segmented_get_group(int g, int *cls_lo, int *cls_hi, int *cfg);
+ap_status ap_load_tuning(const char *path);
 
 /*
  * Request server: sort requests from any number of host threads, batched as

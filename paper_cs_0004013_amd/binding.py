@@ -12,6 +12,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libapsort.so")
+TUNE_TABLE = os.path.join(HERE, "tune_gfx950.txt")   # written by paper_cs_0004013_amd.autotune
 
 AP_OK = 0
 STATUS = {0: "AP_OK", 1: "AP_ERR_INVALID", 2: "AP_ERR_NOMEM", 3: "AP_ERR_HIP", 4: "AP_ERR_BUDGET",
@@ -43,7 +44,11 @@ SIGNATURES = [
     ("ap_sort_u32_segmented", _I, [_VP, _SZ, _VP, _I, _VP, _VP]),
     ("ap_segmented_workspace_bytes", _SZ, [_SZ, _I]),
     ("ap_segmented_num_configs", _I, []),
+    ("ap_segmented_config_info", _I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     ("ap_segmented_set_config", _I, [_I]),
+    ("ap_segmented_set_group", _I, [_I, _I, _I, _I]),
+    ("ap_segmented_get_group", _I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    ("ap_load_tuning", _I, [ctypes.c_char_p]),
     ("ap_server_create", _I, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)]),
     ("ap_server_submit", _I, [_VP, _VP, _VP, _SZ, _I, _VP, _U64P]),
     ("ap_server_submit_flags", _I, [_VP, _VP, _VP, _SZ, _I, _VP, ctypes.c_uint, _U64P]),
@@ -80,6 +85,10 @@ def lib() -> ctypes.CDLL:
             f.restype = res
             f.argtypes = args
         _bind_extra(L)
+        if os.path.exists(TUNE_TABLE):
+            st = L.ap_load_tuning(TUNE_TABLE.encode())
+            if st != AP_OK:
+                raise ApError(st, "ap_load_tuning", L.ap_last_error().decode(errors="replace"))
         _lib = L
     return _lib
 
@@ -209,6 +218,37 @@ def ap_segmented_num_configs() -> int:
 
 def ap_segmented_set_config(cfg: int) -> None:
     check(lib().ap_segmented_set_config(cfg), "ap_segmented_set_config")
+
+
+SEG_GROUPS = 4
+
+
+def ap_segmented_config_info(cfg: int) -> tuple[int, int, int]:
+    """(digit bits, waves per workgroup, keys per lane) of a compiled-in configuration."""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib().ap_segmented_config_info(cfg, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+          "ap_segmented_config_info")
+    return a.value, b.value, c.value
+
+
+def segmented_groups() -> list[tuple[int, int, int]]:
+    """Current (cls_lo, cls_hi, cfg) of every length group."""
+    out = []
+    for g in range(SEG_GROUPS):
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().ap_segmented_get_group(g, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "ap_segmented_get_group")
+        out.append((a.value, b.value, c.value))
+    return out
+
+
+def set_segmented_groups(groups) -> None:
+    for g, (lo, hi, cfg) in enumerate(groups):
+        check(lib().ap_segmented_set_group(g, lo, hi, cfg), "ap_segmented_set_group")
+
+
+def ap_load_tuning(path: str) -> None:
+    check(lib().ap_load_tuning(path.encode()), "ap_load_tuning")
 
 
 AP_SUBMIT_INJECT_FAULT = 1

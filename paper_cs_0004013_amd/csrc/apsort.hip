@@ -121,18 +121,35 @@ ap_status check_lane_order(hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- configuration
-// Digit width and tile shape of the single-array sort.  8-bit digits (4 passes for 32-bit keys);
-// large arrays use 8192-key tiles (4 waves x 32 keys per lane), small ones 2048-key tiles so that
-// the grid still covers every compute unit.
+// Digit width and tile shapes of the single-array sort.  8-bit digits (4 passes for 32-bit keys).
+// Tiles grow with n: larger tiles mean fewer tiles, so the look-back chain between tiles is
+// shorter relative to the time between tile starts, and a bucket's run in a tile is longer, so
+// the scatter writes longer contiguous pieces.  The largest tile (16 waves x 32 keys per lane,
+// 148 KiB of LDS, one workgroup per CU) is used from 2^25 keys on; small arrays use small tiles
+// so that the grid still covers every compute unit.
 constexpr int kBits = 8;
 constexpr int kRadix = 1 << kBits;
 constexpr int kDigits = (32 + kBits - 1) / kBits;
 constexpr int kHistThreads = 512;
 constexpr uint32_t kHistCopies = 32;  // copies of the global counters (contention / 32)
-constexpr int kWaves = 4;
-constexpr int kIptLarge = 32;
-constexpr int kIptSmall = 8;
-constexpr uint32_t kSmallN = 1u << 22;
+
+struct PassShape {
+  int waves, ipt;
+};
+static const PassShape kShapes[] = {{4, 8}, {4, 16}, {8, 32}, {16, 32}};  // 2K, 4K, 16K, 32K keys
+
+static int shape_for(size_t n) {
+  if (n >= ((size_t)1 << 25)) return 3;
+  if (n >= ((size_t)1 << 22)) return 2;
+  if (n >= ((size_t)1 << 19)) return 1;
+  return 0;
+}
+// The mask rank needs extra LDS that the 32K-key tile cannot spare; it uses the 16K-key shape.
+static int shape_for_rank(size_t n, bool atomic_rank) {
+  const int sh = shape_for(n);
+  return (!atomic_rank && sh == 3) ? 2 : sh;
+}
+static int tile_keys(int sh) { return kShapes[sh].waves * 64 * kShapes[sh].ipt; }
 
 // LDS copies of the counters in k_hist_plan: as many as fit in 64 KiB, at most 16.
 template <int BITS>
@@ -142,17 +159,16 @@ constexpr int hist_lcopies() {
   return c < 1 ? 1 : (c > 16 ? 16 : c);
 }
 
-static int tile_keys_for(size_t n) { return (n >= kSmallN ? kIptLarge : kIptSmall) * kWaves * 64; }
-
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace layout (bytes from the 256-byte aligned base):
 //   [hist copies*D*R u32][base D*R u32][plan 32 u32][done 1 u32 | pad][tile counters 8 u32 | pad]
 //   [status D * ntiles * R u32][tmp n u32]
-// hist and done are self-clearing; tile counters and status are cleared by k_hist_plan.
+// hist and done are self-clearing; tile counters and the used part of status are cleared by
+// k_hist_plan.  Status capacity covers the smaller tile of either rank primitive.
 Layout layout_for(size_t n) {
   Layout L{};
-  const int T = tile_keys_for(n);
+  const int T = std::min(tile_keys(shape_for_rank(n, true)), tile_keys(shape_for_rank(n, false)));
   L.tile_keys = T;
   L.ntiles = (uint32_t)((n + T - 1) / T);
   size_t off = 0;
@@ -162,11 +178,26 @@ Layout layout_for(size_t n) {
   L.done = off;   off += 256;
   L.tctr = off;   off += 256;
   L.status = off; off += align_up(sizeof(uint32_t) * (size_t)kDigits * L.ntiles * kRadix, 256);
-  L.zero_bytes = off - L.tctr;  // tile counters + status, cleared every call
+  L.zero_bytes = off - L.tctr;  // upper bound of the region k_hist_plan clears
   L.tmp = off;    off += align_up(sizeof(uint32_t) * n, 256);
   L.total = off;
   L.init_bytes = L.tctr;        // hist, base, plan, done: zeroed once at workspace creation
   return L;
+}
+
+template <int W, int I>
+static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out, uint32_t* tmp,
+                        uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d, uint32_t* st_d,
+                        uint32_t* tctr) {
+  if constexpr (W * 64 * I <= 16384) {
+    if (!atomic_rank) {
+      hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d, plan,
+                         base_d, st_d, tctr);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_ATOMIC>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d, plan, base_d,
+                     st_d, tctr);
 }
 
 // ---------------------------------------------------------------- launch sequence
@@ -183,6 +214,11 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
   const uint32_t nn = (uint32_t)n;
   const int cus = device_cus();
   const int inplace = (d_in == d_out) ? 1 : 0;
+  const bool atomic_rank = lane_order_ok();
+  const int sh = shape_for_rank(n, atomic_rank);
+  const int T = tile_keys(sh);
+  const uint32_t ntiles = (uint32_t)((n + T - 1) / T);
+  const size_t zero_bytes = 256 + align_up(sizeof(uint32_t) * (size_t)kDigits * ntiles * kRadix, 256);
 
   // A1 + A2
   {
@@ -192,33 +228,23 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
     prof_begin(AP_KIND_HIST, s);
     hipLaunchKernelGGL((k_hist_plan<kBits, kHistThreads, hist_lcopies<kBits>()>), dim3(g), dim3(kHistThreads), 0, s,
                        d_in, nn,
-                       hist, base, plan, done, reinterpret_cast<uint4*>(tctr), (uint32_t)(L.zero_bytes / 16),
+                       hist, base, plan, done, reinterpret_cast<uint4*>(tctr), (uint32_t)(zero_bytes / 16),
                        inplace, (uint32_t*)nullptr, kHistCopies);
     prof_end(s);
     ap_status st = check_launch(s, "k_hist_plan");
     if (st != AP_OK) return st;
   }
   // A3-A6: one launch per digit; passes the plan skips exit at once
-  const bool atomic_rank = lane_order_ok();
   for (int d = 0; d < kDigits; ++d) {
-    uint32_t* st_d = status + (size_t)d * L.ntiles * kRadix;
+    uint32_t* st_d = status + (size_t)d * ntiles * kRadix;
     const uint32_t* base_d = base + d * kRadix;
     prof_begin(AP_KIND_PASS + d, s);
-    const dim3 grid(L.ntiles), block(kWaves * 64);
-    if (L.tile_keys == kIptLarge * kWaves * 64) {
-      if (atomic_rank)
-        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptLarge, RANK_ATOMIC>), grid, block, 0, s, d_in, d_out, tmp, nn,
-                           d, plan, base_d, st_d, tctr);
-      else
-        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptLarge, RANK_MATCH>), grid, block, 0, s, d_in, d_out, tmp, nn,
-                           d, plan, base_d, st_d, tctr);
-    } else {
-      if (atomic_rank)
-        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptSmall, RANK_ATOMIC>), grid, block, 0, s, d_in, d_out, tmp, nn,
-                           d, plan, base_d, st_d, tctr);
-      else
-        hipLaunchKernelGGL((k_pass<kBits, kWaves, kIptSmall, RANK_MATCH>), grid, block, 0, s, d_in, d_out, tmp, nn,
-                           d, plan, base_d, st_d, tctr);
+    const dim3 grid(ntiles);
+    switch (sh) {
+      case 3: launch_pass<16, 32>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
+      case 2: launch_pass<8, 32>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
+      case 1: launch_pass<4, 16>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
+      default: launch_pass<4, 8>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
     }
     prof_end(s);
     ap_status st = check_launch(s, "k_pass");

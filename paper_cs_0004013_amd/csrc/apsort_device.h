@@ -97,4 +97,48 @@ __device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t* sc
   return total;
 }
 
+// Tile bucket offsets from per-wave bucket counts, with one block-wide scan.
+// On entry cnt[w*R + b] = number of keys of wave w in bucket b.  On exit cnt[w*R + b] = tile-local
+// start of wave w's run of bucket b, i.e. the exclusive prefix over (bucket, wave) in bucket-major
+// order, so runs of one bucket follow wave order (stable); lbase[b] = start of bucket b and
+// lbase[R] = number of keys in the tile.  scratch needs WAVES words.  Starts and ends with a
+// workgroup barrier.
+template <int R, int WAVES>
+__device__ __forceinline__ void tile_bucket_offsets(uint32_t* cnt, uint32_t* lbase, uint32_t* scratch) {
+  constexpr int THREADS = WAVES * 64, N = R * WAVES, E = (N + THREADS - 1) / THREADS;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __syncthreads();
+  uint32_t v[E];
+  uint32_t sum = 0u;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int f = tid * E + e;
+    v[e] = f < N ? cnt[(f % WAVES) * R + f / WAVES] : 0u;
+    sum += v[e];
+  }
+  uint32_t x = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) scratch[wid] = x;
+  __syncthreads();
+  uint32_t run = x - sum;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) run += (w < wid) ? scratch[w] : 0u;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int f = tid * E + e;
+    if (f < N) {
+      const int b = f / WAVES, w = f % WAVES;
+      cnt[w * R + b] = run;
+      if (w == 0) lbase[b] = run;
+    }
+    run += v[e];
+  }
+  if (tid == THREADS - 1) lbase[R] = run;
+  __syncthreads();
+}
+
 }  // namespace aps

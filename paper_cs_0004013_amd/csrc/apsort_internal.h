@@ -35,10 +35,15 @@ bool prof_active();
 // Segmented sort (apsort_seg.hip), shared with the request server.
 struct SegDesc;
 struct SegCtl;
-void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t nwork, SegCtl* ctl);
+struct SegGroup {
+  int cls_lo, cls_hi, cfg;  // floor(log2(length)) range and kernel configuration
+};
+void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
+                    int cls_hi, int grp, SegCtl* ctl);
 int seg_workgroups(int cfg, uint32_t nwork);
 int seg_tile_keys(int cfg);
-int seg_config();
+void seg_groups(SegGroup* out);  // kSegGroups entries
+void seg_reset(hipStream_t s, SegCtl* ctl);
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
                        const Layout& L, hipStream_t s);
 

@@ -216,10 +216,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   uint32_t* __restrict__ dst = dsel == SEL_OUT ? out : tmp;
   const int shift = d * BITS;
 
-  __shared__ uint32_t s_cnt[WAVES * R];  // per-wave bucket counters, then per-wave start offsets
-  __shared__ uint32_t s_delta[R];        // bucket totals -> tile-local bucket starts -> global delta
+  __shared__ uint32_t s_cnt[WAVES * R];  // per-wave bucket counters, then per-wave run starts
+  __shared__ uint32_t s_lbase[R + 1];    // tile-local bucket starts (+ tile size)
+  __shared__ uint32_t s_delta[R];        // global start minus tile-local start, per bucket
   __shared__ uint32_t s_stage[T];        // keys in tile-sorted order
-  __shared__ uint32_t s_scan[THREADS / 64];
+  __shared__ uint32_t s_scan[WAVES];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_bins[RANK == RANK_MATCH ? WAVES * R : 1];  // per-wave bucket lane masks
 
@@ -276,45 +277,28 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
       if (peers == 0u) cnt[v] = c + (uint32_t)__popcll(m);
     }
   }
-  __syncthreads();
 
-  // ---- tile bucket totals; publish them for the look-back of later tiles ----
+  // ---- tile-local run starts (one scan over bucket-major, wave-minor counts); publish the
+  //      tile's bucket counts for the look-back of later tiles ----
+  tile_bucket_offsets<R, WAVES>(s_cnt, s_lbase, s_scan);
   uint32_t tot[BPT];
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
     const int b = tid + i * THREADS;
     tot[i] = 0u;
     if (b < R) {
-      uint32_t s = 0u;
-#pragma unroll
-      for (int w = 0; w < WAVES; ++w) {
-        const uint32_t c = s_cnt[w * R + b];
-        s_cnt[w * R + b] = s;
-        s += c;
-      }
-      tot[i] = s;
-      s_delta[b] = s;
-      if (tile == 0u) st_agent(status + b, kFlagPrefix | (g_base[b] + s));
-      else st_agent(status + (size_t)tile * R + b, kFlagAgg | s);
+      tot[i] = s_lbase[b + 1] - s_lbase[b];
+      if (tile == 0u) st_agent(status + b, kFlagPrefix | (g_base[b] + tot[i]));
+      else st_agent(status + (size_t)tile * R + b, kFlagAgg | tot[i]);
     }
   }
-  lds_exclusive_scan<R, THREADS>(s_delta, s_scan);  // s_delta = tile-local bucket starts
-#pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    const int b = tid + i * THREADS;
-    if (b < R) {
-      const uint32_t lb = s_delta[b];
-#pragma unroll
-      for (int w = 0; w < WAVES; ++w) s_cnt[w * R + b] += lb;
-    }
-  }
-  __syncthreads();
 
   // ---- A5 (first half): reorder the tile in LDS; independent of the global offsets ----
+  uint32_t* cnt_w = s_cnt + wid * R;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const uint32_t v = (k[j] >> shift) & (R - 1);
-    s_stage[cnt[v] + r[j]] = k[j];
+    s_stage[cnt_w[v] + r[j]] = k[j];
   }
 
   // ---- A3: decoupled look-back for each bucket's global start ----
@@ -354,7 +338,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
         }
         st_agent(status + (size_t)tile * R + b, kFlagPrefix | (excl + tot[i]));
       }
-      s_delta[b] = excl - s_delta[b];
+      s_delta[b] = excl - s_lbase[b];
     }
   }
   __syncthreads();

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -36,32 +37,55 @@ constexpr int seg_lcopies() {
 }
 
 template <int BITS, int WAVES, int IPT>
-static void launch_seg_sort(dim3 grid, hipStream_t s, const SegDesc* order, uint32_t nwork, SegCtl* ctl) {
-  hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, seg_lcopies<BITS>()>), grid, dim3(WAVES * 64), 0, s, order,
-                     nwork, ctl);
+static void launch_seg_sort(dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
+                            int cls_hi, int grp, SegCtl* ctl) {
+  hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, seg_lcopies<BITS>()>), grid, dim3(WAVES * 64), 0, s, order, lo,
+                     hi, cls_lo, cls_hi, grp, ctl);
 }
 
-void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t nwork, SegCtl* ctl) {
+// One persistent kernel of configuration cfg over work items [lo, hi) (or, with hi == ~0u, over
+// the device-built work order's length classes [cls_lo, cls_hi]), taking items from head[grp].
+void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
+                    int cls_hi, int grp, SegCtl* ctl) {
   switch (cfg) {
-    case 1: launch_seg_sort<8, 16, 8>(grid, s, order, nwork, ctl); break;
-    case 2: launch_seg_sort<8, 4, 16>(grid, s, order, nwork, ctl); break;
-    case 3: launch_seg_sort<8, 4, 8>(grid, s, order, nwork, ctl); break;
-    case 4: launch_seg_sort<4, 4, 8>(grid, s, order, nwork, ctl); break;
-    case 5: launch_seg_sort<8, 8, 8>(grid, s, order, nwork, ctl); break;
-    case 6: launch_seg_sort<6, 4, 8>(grid, s, order, nwork, ctl); break;
-    default: launch_seg_sort<8, 8, 16>(grid, s, order, nwork, ctl); break;
+    case 1: launch_seg_sort<8, 16, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 2: launch_seg_sort<8, 4, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 3: launch_seg_sort<8, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 4: launch_seg_sort<4, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 5: launch_seg_sort<8, 8, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 6: launch_seg_sort<6, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    default: launch_seg_sort<8, 8, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
   }
 }
 
+// Resident workgroups per CU of each configuration (LDS and registers allow two workgroups of up
+// to 512 threads, one of 1024), times the CU count, capped by the work.
 int seg_workgroups(int cfg, uint32_t nwork) {
-  const int per_cu = (kSegCfgs[cfg].waves * 64 >= 1024) ? 1 : 2;
+  const int per_cu = (kSegCfgs[cfg].waves * 64 >= 1024) ? 1 : (kSegCfgs[cfg].waves <= 4 ? 4 : 2);
   return (int)std::max<uint32_t>(1u, std::min<uint32_t>(nwork, (uint32_t)(per_cu * device_cus())));
 }
 
 int seg_tile_keys(int cfg) { return kSegCfgs[cfg].waves * 64 * kSegCfgs[cfg].ipt; }
 
-static int g_seg_cfg = 0;  // configuration of the persistent kernel (set by the tuner)
-int seg_config() { return g_seg_cfg; }
+void seg_reset(hipStream_t s, SegCtl* ctl) { hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, s, ctl); }
+
+// Length groups: group g sorts the segments whose floor(log2(length)) lies in [cls_lo, cls_hi] with
+// kernel configuration cfg.  Defaults: one-tile and longer segments with 8192-key tiles, short
+// ones with 2048-key tiles; the tuner rewrites the table (ap_segmented_set_group, ap_load_tuning).
+static std::mutex g_grp_mu;
+static SegGroup g_groups[kSegGroups] = {{13, 31, 0}, {11, 12, 0}, {1, 10, 3}, {1, 0, 0}};
+static int g_groups_version = 0;  // bumped on every change (invalidates captured graphs)
+
+int seg_groups_version() {
+  std::lock_guard<std::mutex> lk(g_grp_mu);
+  return g_groups_version;
+}
+
+void seg_groups(SegGroup* out) {
+  std::lock_guard<std::mutex> lk(g_grp_mu);
+  for (int g = 0; g < kSegGroups; ++g) out[g] = g_groups[g];
+}
+
 
 // Workspace: [SegCtl | pad to 256][order: nseg descriptors | pad][tmp n_total u32]
 struct SegLayout {
@@ -153,8 +177,16 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
                      d_status);
   hipLaunchKernelGGL(k_seg_fill, dim3(g1), dim3(256), 0, s, d_off, (uint32_t)nseg, (uint32_t)n_total, ctl, d_keys,
                      tmp, order);
-  launch_seg_cfg(cfg, dim3(seg_workgroups(cfg, (uint32_t)nseg)), s, order, ~0u, ctl);
+  SegGroup grp[kSegGroups];
+  seg_groups(grp);
+  for (int g = 0; g < kSegGroups; ++g) {
+    if (grp[g].cls_lo > grp[g].cls_hi) continue;
+    launch_seg_cfg(grp[g].cfg, dim3(seg_workgroups(grp[g].cfg, (uint32_t)nseg)), s, order, 0u, ~0u, grp[g].cls_lo,
+                   grp[g].cls_hi, g, ctl);
+  }
+  seg_reset(s, ctl);
   prof_end(s);
+  (void)cfg;
   return check_launch(s, "k_seg_sort");
 }
 
@@ -178,7 +210,7 @@ ap_status ap_sort_u32_segmented(uint32_t* d_keys, size_t n_total, const uint32_t
   SegEntry* ent = nullptr;
   ap_status st = seg_entry(s, L.total, &ent);
   if (st != AP_OK) return st;
-  const int cfg = g_seg_cfg;
+  const int cfg = seg_groups_version();
 
   // Replay a captured graph when the call repeats the previous one on this stream; capture
   // otherwise (only on a non-default stream that is not itself being captured).
@@ -231,10 +263,67 @@ size_t ap_segmented_workspace_bytes(size_t n_total, int nseg) {
 
 ap_status ap_segmented_set_config(int cfg) {
   if (cfg < 0 || cfg >= kNumSegCfgs) return fail(AP_ERR_INVALID, "config index out of range");
-  g_seg_cfg = cfg;
+  std::lock_guard<std::mutex> lk(g_grp_mu);
+  for (auto& g : g_groups) g.cfg = cfg;
+  ++g_groups_version;
+  return AP_OK;
+}
+
+ap_status ap_segmented_set_group(int g, int cls_lo, int cls_hi, int cfg) {
+  if (g < 0 || g >= kSegGroups) return fail(AP_ERR_INVALID, "group index out of range");
+  if (cfg < 0 || cfg >= kNumSegCfgs) return fail(AP_ERR_INVALID, "config index out of range");
+  if (cls_lo < 1 || cls_hi > 31) return fail(AP_ERR_INVALID, "length classes must lie in [1, 31]");
+  std::lock_guard<std::mutex> lk(g_grp_mu);
+  g_groups[g] = SegGroup{cls_lo, cls_hi, cfg};
+  ++g_groups_version;
+  return AP_OK;
+}
+
+ap_status ap_segmented_get_group(int g, int* cls_lo, int* cls_hi, int* cfg) {
+  if (g < 0 || g >= kSegGroups || !cls_lo || !cls_hi || !cfg) return fail(AP_ERR_INVALID, "bad argument");
+  std::lock_guard<std::mutex> lk(g_grp_mu);
+  *cls_lo = g_groups[g].cls_lo;
+  *cls_hi = g_groups[g].cls_hi;
+  *cfg = g_groups[g].cfg;
+  return AP_OK;
+}
+
+ap_status ap_load_tuning(const char* path) {
+  if (!path) return fail(AP_ERR_INVALID, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(AP_ERR_INVALID, "cannot open tuning table %s", path);
+  SegGroup next[kSegGroups];
+  for (auto& g : next) g = SegGroup{1, 0, 0};
+  char line[256];
+  int seen = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    int g, lo, hi, c;
+    if (std::sscanf(line, "%d %d %d %d", &g, &lo, &hi, &c) != 4) continue;
+    if (g < 0 || g >= kSegGroups || c < 0 || c >= kNumSegCfgs || lo < 1 || hi > 31) {
+      std::fclose(f);
+      return fail(AP_ERR_INVALID, "bad tuning line: %s", line);
+    }
+    next[g] = SegGroup{lo, hi, c};
+    ++seen;
+  }
+  std::fclose(f);
+  if (!seen) return fail(AP_ERR_INVALID, "no tuning entries in %s", path);
+  std::lock_guard<std::mutex> lk(g_grp_mu);
+  for (int g = 0; g < kSegGroups; ++g) g_groups[g] = next[g];
+  ++g_groups_version;
   return AP_OK;
 }
 
 int ap_segmented_num_configs(void) { return kNumSegCfgs; }
+
+ap_status ap_segmented_config_info(int cfg, int* digit_bits, int* waves, int* keys_per_lane) {
+  if (cfg < 0 || cfg >= kNumSegCfgs || !digit_bits || !waves || !keys_per_lane)
+    return fail(AP_ERR_INVALID, "bad argument");
+  *digit_bits = kSegCfgs[cfg].bits;
+  *waves = kSegCfgs[cfg].waves;
+  *keys_per_lane = kSegCfgs[cfg].ipt;
+  return AP_OK;
+}
 
 }  // extern "C"

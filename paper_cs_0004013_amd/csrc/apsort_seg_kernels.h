@@ -21,8 +21,9 @@ namespace aps {
 
 __device__ __forceinline__ int seg_class(uint32_t len) { return 31 - __clz(len); }
 
-// Pass 1: validate offsets, count segments per length class; the last workgroup turns the counts
-// into a longest-first order of classes and reports invalid offsets through d_status.
+// Pass 1: validate offsets (off[s] <= off[s+1] <= n_total for every s), count segments per length
+// class; the last workgroup turns the counts into a longest-first order of classes, or into an
+// empty order when any offset was invalid, and reports the outcome through d_status.
 __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict__ off, uint32_t nseg,
                                                      uint32_t n_total, SegCtl* __restrict__ ctl,
                                                      uint32_t* __restrict__ d_status) {
@@ -54,15 +55,17 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict
   __syncthreads();
   if (!s_last) return;
   if (tid == 0) {
+    // Any invalid offset makes segments overlap or leave the buffer: then nothing is sorted.
+    const uint32_t bad = ld_agent(&ctl->bad);
     uint32_t run = 0;
     for (int c = kSegBuckets - 1; c >= 0; --c) {  // longest class first
-      const uint32_t k = ld_agent(&ctl->count[c]);
+      const uint32_t k = bad ? 0u : ld_agent(&ctl->count[c]);
+      ctl->count[c] = k;
       ctl->start[c] = run;
       run += k;
     }
     ctl->nwork = run;
     ctl->done = 0u;
-    const uint32_t bad = ld_agent(&ctl->bad);
     if (d_status) d_status[0] = bad ? (uint32_t)AP_ERR_INVALID : 0u;
   }
 }
@@ -72,6 +75,7 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict
 __global__ __launch_bounds__(256) void k_seg_fill(const uint32_t* __restrict__ off, uint32_t nseg, uint32_t n_total,
                                                  SegCtl* __restrict__ ctl, uint32_t* keys, uint32_t* tmp,
                                                  SegDesc* __restrict__ order) {
+  if (ctl->bad) return;  // invalid offsets: no work
   for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < nseg; s += gridDim.x * 256) {
     const uint32_t a = off[s], b = off[s + 1];
     if (b < a || b > n_total) continue;
@@ -107,7 +111,7 @@ struct SegSmem {
   } u;
   uint32_t base[HW];     // segment-wide exclusive bucket starts, per digit
   uint32_t running[R];   // next free slot of each bucket in the current digit sweep
-  uint32_t lbase[R];     // tile-local bucket starts
+  uint32_t lbase[R + 1]; // tile-local bucket starts (+ tile size)
   uint32_t tot[R];       // tile bucket totals
   uint32_t scan[WAVES];
   uint32_t flag[kMaxDigits];
@@ -129,8 +133,8 @@ __device__ __forceinline__ void seg_splitters(const SegDesc& dsc, uint32_t len) 
 }
 
 // Tile rank of the keys k[] (wave-striped order) by the digit at `shift`: per-wave LDS counters
-// with lane-ordered atomics, then per-bucket wave prefixes, tile totals (tot) and tile-local
-// starts (lbase); finally cnt[w][v] holds the tile-local start of wave w's run of bucket v.
+// with lane-ordered atomics, then one scan gives cnt[w][v] = tile-local start of wave w's run of
+// bucket v, lbase (bucket starts) and tot (bucket totals).
 template <int BITS, int WAVES, int IPT, int LCOPIES>
 __device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>& sm, const uint32_t (&k)[IPT],
                                               uint32_t (&r)[IPT], int shift) {
@@ -144,46 +148,36 @@ __device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>
     const uint32_t v = (k[j] >> shift) & (R - 1);
     r[j] = __hip_atomic_fetch_add(&cnt[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   }
-  __syncthreads();
-  for (int b = tid; b < R; b += THREADS) {
-    uint32_t s = 0u;
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      const uint32_t c = sm.u.p.cnt[w * R + b];
-      sm.u.p.cnt[w * R + b] = s;
-      s += c;
-    }
-    sm.tot[b] = s;
-    sm.lbase[b] = s;
-  }
-  lds_exclusive_scan<R, THREADS>(sm.lbase, sm.scan);
-  for (int b = tid; b < R; b += THREADS) {
-    const uint32_t lb = sm.lbase[b];
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) sm.u.p.cnt[w * R + b] += lb;
-  }
+  tile_bucket_offsets<R, WAVES>(sm.u.p.cnt, sm.lbase, sm.scan);
+  for (int b = tid; b < R; b += THREADS) sm.tot[b] = sm.lbase[b + 1] - sm.lbase[b];
   __syncthreads();
 }
 
-// Persistent segmented sort over the descriptors order[0..nwork), longest first.  nwork is read
-// from ctl when nwork_arg is ~0u (work list built on the device) and taken from the argument
-// otherwise (work list built on the host).
+// Persistent segmented sort over the descriptors order[lo..hi), longest first.  With
+// item_hi == ~0u the range is that of the length classes [cls_lo, cls_hi] in the device-built
+// work order (classes are stored longest first); otherwise it is [item_lo, item_hi).  Work items
+// are taken from ctl->head[grp].
 template <int BITS, int WAVES, int IPT, int LCOPIES>
-__global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restrict__ order, uint32_t nwork_arg,
+__global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restrict__ order, uint32_t item_lo,
+                                                        uint32_t item_hi, int cls_lo, int cls_hi, int grp,
                                                         SegCtl* __restrict__ ctl) {
   using SM = SegSmem<BITS, WAVES, IPT, LCOPIES>;
   constexpr int R = SM::R, D = SM::D, T = SM::T, HW = SM::HW, THREADS = WAVES * 64;
   constexpr int CS = HW + 1;
   __shared__ SM sm;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const uint32_t nwork = nwork_arg == ~0u ? ctl->nwork : nwork_arg;
+  uint32_t lo = item_lo, hi = item_hi;
+  if (item_hi == ~0u) {
+    lo = ctl->start[cls_hi];
+    hi = ctl->start[cls_lo] + ctl->count[cls_lo];
+  }
 
   while (true) {
     __syncthreads();
-    if (tid == 0) sm.item = add_agent(&ctl->head, 1u);
+    if (tid == 0) sm.item = lo + add_agent(&ctl->head[grp], 1u);
     __syncthreads();
     const uint32_t item = sm.item;
-    if (item >= nwork) break;
+    if (item >= hi) break;
     const SegDesc dsc = order[item];
     const uint32_t len = dsc.n;
 
@@ -328,21 +322,27 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
     seg_splitters<THREADS>(dsc, len);
   }
 
-  // last workgroup out resets the control block for the next call
+  // last workgroup out resets this group's counters for the next call
   if (tid == 0) {
     __threadfence();
-    if (add_agent(&ctl->done2, 1u) == gridDim.x - 1) {
-      __threadfence();
-      for (int c = 0; c < kSegBuckets; ++c) {
-        ctl->count[c] = 0u;
-        ctl->start[c] = 0u;
-        ctl->cursor[c] = 0u;
-      }
-      ctl->nwork = 0u;
-      ctl->head = 0u;
-      ctl->bad = 0u;
-      st_agent(&ctl->done2, 0u);
+    if (add_agent(&ctl->done2[grp], 1u) == gridDim.x - 1) {
+      st_agent(&ctl->head[grp], 0u);
+      st_agent(&ctl->done2[grp], 0u);
     }
+  }
+}
+
+// Clears the per-call part of the control block after every group kernel has run.
+__global__ void k_seg_reset(SegCtl* __restrict__ ctl) {
+  const int t = threadIdx.x;
+  if (t < kSegBuckets) {
+    ctl->count[t] = 0u;
+    ctl->start[t] = 0u;
+    ctl->cursor[t] = 0u;
+  }
+  if (t == 0) {
+    ctl->nwork = 0u;
+    ctl->bad = 0u;
   }
 }
 

@@ -6,6 +6,7 @@
 namespace aps {
 
 constexpr int kSegBuckets = 32;  // work-list classes: floor(log2(length))
+constexpr int kSegGroups = 4;    // length groups, each sorted by its own kernel configuration
 
 // Control block of the segmented sort (device memory, zero between calls).
 struct SegCtl {
@@ -13,11 +14,11 @@ struct SegCtl {
   uint32_t start[kSegBuckets];   // first slot of each class in the work order (longest first)
   uint32_t cursor[kSegBuckets];  // fill cursors
   uint32_t nwork;                // segments to sort (length >= 2 and valid)
-  uint32_t head;                 // next work item
-  uint32_t done;                 // completion counters for last-workgroup patterns
-  uint32_t done2;
+  uint32_t done;                 // completion counter of k_seg_classify's last-workgroup pattern
   uint32_t bad;                  // 1 when some offsets were invalid
-  uint32_t pad[3];
+  uint32_t pad0;
+  uint32_t head[kSegGroups];     // next work item of each length group's kernel
+  uint32_t done2[kSegGroups];    // exit counters of each group's kernel
 };
 
 // One unit of work of the persistent sort: sort src[0..n) into dst[0..n) (src == dst allowed),

@@ -35,8 +35,7 @@ class HipExecutor : public srv::Executor {
 
   ap_status init(int nslots, size_t budget, int max_batch) {
     if (hipGetDevice(&dev_) != hipSuccess) return fail(AP_ERR_HIP, "hipGetDevice failed");
-    cfg_ = seg_config();
-    tile_ = (size_t)seg_tile_keys(cfg_);
+    tile_ = 2048;  // smallest tile of any configuration: longer requests get scratch
     max_batch_ = max_batch;
     header_ = up256s(sizeof(SegCtl)) + up256s(sizeof(SegDesc) * (size_t)max_batch);
     const size_t arena = (budget / (size_t)nslots) / 256 * 256;
@@ -105,7 +104,25 @@ class HipExecutor : public srv::Executor {
     }
     hipError_t e = hipMemcpyAsync(sl.d_desc, sl.h_desc, sizeof(SegDesc) * cnt, hipMemcpyHostToDevice, sl.stream);
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-    launch_seg_cfg(cfg_, dim3(seg_workgroups(cfg_, cnt)), sl.stream, sl.d_desc, cnt, sl.ctl);
+    // The descriptors are sorted longest first, so each length group is a contiguous item range
+    // (lengths 0 and 1 count as class 1).
+    SegGroup grp[kSegGroups];
+    seg_groups(grp);
+    for (int g = 0; g < kSegGroups; ++g) {
+      if (grp[g].cls_lo > grp[g].cls_hi) continue;
+      uint32_t lo = cnt, hi = 0;
+      for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t n = sl.h_desc[i].n;
+        const int c = n < 2 ? 1 : 31 - __builtin_clz(n);
+        if (c >= grp[g].cls_lo && c <= grp[g].cls_hi) {
+          lo = std::min(lo, i);
+          hi = i + 1;
+        }
+      }
+      if (lo >= hi) continue;
+      launch_seg_cfg(grp[g].cfg, dim3(seg_workgroups(grp[g].cfg, hi - lo)), sl.stream, sl.d_desc, lo, hi, 0, 0, g,
+                     sl.ctl);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_seg_sort");
     e = hipEventRecord(sl.ev, sl.stream);
@@ -137,7 +154,6 @@ class HipExecutor : public srv::Executor {
 
  private:
   int dev_ = 0;
-  int cfg_ = 0;
   size_t tile_ = 8192;
   int max_batch_ = 256;
   size_t header_ = 0;

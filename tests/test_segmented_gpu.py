@@ -17,14 +17,14 @@ def _run(keys: np.ndarray, offsets: np.ndarray, cfg: int | None = None, pad_fron
     t_keys, _ = to_dev(keys, pad_front)
     t_off = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.uint32).view(np.int32)).to("cuda")
     t_st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    saved = binding.segmented_groups()
     if cfg is not None:
         binding.ap_segmented_set_config(cfg)
     try:
         binding.ap_sort_u32_segmented(t_keys, t_off, t_st)
         torch.cuda.synchronize()
     finally:
-        if cfg is not None:
-            binding.ap_segmented_set_config(0)
+        binding.set_segmented_groups(saved)
     return to_host(t_keys), int(to_host(t_st)[0])
 
 
@@ -49,6 +49,19 @@ def test_log_uniform_batch_512():
     L = inputs.segment_lengths(512, seed=0)
     keys, off = _batch(L)
     _check(keys, off)
+
+
+def test_group_split_table():
+    """A custom four-group table (different configurations per length range) gives oracle results."""
+    from paper_cs_0004013_amd import binding
+    saved = binding.segmented_groups()
+    try:
+        binding.set_segmented_groups([(15, 31, 1), (12, 14, 5), (9, 11, 2), (1, 8, 4)])
+        L = inputs.segment_lengths(200, seed=8, lo=2, hi=1 << 17)
+        keys, off = _batch(L)
+        _check(keys, off)
+    finally:
+        binding.set_segmented_groups(saved)
 
 
 @pytest.mark.parametrize("cfg", range(7))
@@ -105,7 +118,13 @@ def test_invalid_offsets_reported():
     bad[2] = bad[1] - 10                 # segment 1 decreasing
     got, status = _run(keys, bad)
     assert status == 1                   # AP_ERR_INVALID
-    assert np.array_equal(got[:1000], np.sort(keys[:1000]))
+    assert np.array_equal(got, keys)     # nothing sorted
+    beyond = off.copy()
+    beyond[-1] = keys.size + 1           # past n_total
+    got, status = _run(keys, beyond)
+    assert status == 1 and np.array_equal(got, keys)
+    got, status = _run(keys, off)        # valid again afterwards (control block was reset)
+    assert status == 0 and np.array_equal(got, oracle.sort_segmented(keys, off.astype(np.uint64)))
 
 
 def test_graph_replay_and_recapture():
