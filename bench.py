@@ -258,6 +258,8 @@ def main() -> int:
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=20000)
     ap.add_argument("--served-rates", default="0.5,0.9,1.25")
+    ap.add_argument("--profile-leg", choices=["segmented", "latency"], default=None,
+                    help="run only that leg (for rocprofv3) and print its result")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -285,6 +287,12 @@ def main() -> int:
                           "launches": 5}), flush=True)
         return 0
     binding.lib()
+    if args.profile_leg == "segmented":
+        print(json.dumps(leg_segmented(binding, torch, np, inputs, steps=3)), flush=True)
+        return 0
+    if args.profile_leg == "latency":
+        print(json.dumps(leg_latency(binding, torch, np, inputs)), flush=True)
+        return 0
 
     def upload(keys):
         return torch.from_numpy(keys.view(np.int32)).to("cuda")
