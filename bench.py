@@ -107,7 +107,7 @@ def leg_latency(binding, torch, np, inputs):
             "gkeys_s_p50": round((1 << 20) / pct(ms, 50) / 1e6, 2)}
 
 
-def leg_segmented(binding, torch, np, inputs, steps: int):
+def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True):
     """4096 segments, lengths log-uniform in [64, 2^18] (seed 0); segment s uses seed s."""
     L = inputs.segment_lengths(4096, seed=0)
     keys, off, _ = inputs.segment_keys(L)
@@ -139,6 +139,8 @@ def leg_segmented(binding, torch, np, inputs, steps: int):
         res["batched_ms_p50"] = round(pct(ms, 50), 4)
         res["batched_gkeys_s"] = round(n / pct(ms, 50) / 1e6, 3)
         res["batched_ok"] = ok
+        if not baseline:
+            return res
         # baseline: one plain ap_sort_u32 per segment, in order, on the same stream
         lib = binding.lib()
         base_ptr = t_work.data_ptr()
@@ -288,7 +290,7 @@ def main() -> int:
         return 0
     binding.lib()
     if args.profile_leg == "segmented":
-        print(json.dumps(leg_segmented(binding, torch, np, inputs, steps=3)), flush=True)
+        print(json.dumps(leg_segmented(binding, torch, np, inputs, steps=3, baseline=False)), flush=True)
         return 0
     if args.profile_leg == "latency":
         print(json.dumps(leg_latency(binding, torch, np, inputs)), flush=True)

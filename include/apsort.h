@@ -279,6 +279,18 @@ ap_status ap_profile_read(double *ms, uint64_t *launches, int nkinds);
 int ap_rank_check_state(void);
 ap_status ap_set_rank_mode(int mode);
 
+/*
+ * Tile shape of the device-wide digit pass (Sec. 3.2 partial sort and
+ * distribution, one digit of the LSD sort of Sec. 3.3.1).  By default the
+ * tile grows with the array: 2K keys below 2^19, 4K below 2^22, 16K below
+ * 2^25, 32K from there on (the mask rank uses 16K where 32K is chosen).
+ * shape: -1 = by size (default), 0..3 = always 2K, 4K, 16K, 32K keys.
+ * Process-wide, for tests and tuning; results do not depend on it.  A
+ * workspace sized by ap_sort_workspace_bytes before a change can be too small
+ * afterwards (AP_ERR_INVALID).
+ */
+ap_status ap_set_pass_shape(int shape);
+
 /* ap_last_error -- thread-local text for the last failure of this thread. */
 const char *ap_last_error(void);
 

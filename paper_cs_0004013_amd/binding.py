@@ -58,6 +58,7 @@ SIGNATURES = [
     ("ap_server_destroy", _I, [_VP]),
     ("ap_rank_check_state", _I, []),
     ("ap_set_rank_mode", _I, [_I]),
+    ("ap_set_pass_shape", _I, [_I]),
     ("ap_last_error", ctypes.c_char_p, []),
     ("ap_version", ctypes.c_char_p, []),
 ]
@@ -323,6 +324,11 @@ def ap_rank_check_state() -> int:
 def ap_set_rank_mode(mode: int) -> None:
     """0 = automatic (atomic rank when the device passed its lane-order check), 1 = mask rank."""
     check(lib().ap_set_rank_mode(mode), "ap_set_rank_mode")
+
+
+def ap_set_pass_shape(shape: int = -1) -> None:
+    """Tile shape of the device-wide digit pass: -1 = by size, 0..3 = 2K/4K/16K/32K keys."""
+    check(lib().ap_set_pass_shape(shape), "ap_set_pass_shape")
 
 
 def ap_release_cache() -> None:

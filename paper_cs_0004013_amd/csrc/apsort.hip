@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -130,7 +131,7 @@ ap_status check_lane_order(hipStream_t s) {
 constexpr int kBits = 8;
 constexpr int kRadix = 1 << kBits;
 constexpr int kDigits = (32 + kBits - 1) / kBits;
-constexpr int kHistThreads = 512;
+constexpr int kHistThreads = 1024;  // one workgroup per CU (grid <= CUs)
 constexpr uint32_t kHistCopies = 32;  // copies of the global counters (contention / 32)
 
 struct PassShape {
@@ -151,6 +152,14 @@ static int shape_for_rank(size_t n, bool atomic_rank) {
 }
 static int tile_keys(int sh) { return kShapes[sh].waves * 64 * kShapes[sh].ipt; }
 
+// Tile shape override (ap_set_pass_shape): -1 = by size.
+static std::atomic<int> g_shape_override{-1};
+static int shape_used(size_t n, bool atomic_rank) {
+  const int o = g_shape_override.load();
+  if (o >= 0) return (!atomic_rank && o == 3) ? 2 : o;
+  return shape_for_rank(n, atomic_rank);
+}
+
 // LDS copies of the counters in k_hist_plan: as many as fit in 64 KiB, at most 16.
 template <int BITS>
 constexpr int hist_lcopies() {
@@ -168,7 +177,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // k_hist_plan.  Status capacity covers the smaller tile of either rank primitive.
 Layout layout_for(size_t n) {
   Layout L{};
-  const int T = std::min(tile_keys(shape_for_rank(n, true)), tile_keys(shape_for_rank(n, false)));
+  const int T = std::min(tile_keys(shape_used(n, true)), tile_keys(shape_used(n, false)));
   L.tile_keys = T;
   L.ntiles = (uint32_t)((n + T - 1) / T);
   size_t off = 0;
@@ -215,15 +224,16 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
   const int cus = device_cus();
   const int inplace = (d_in == d_out) ? 1 : 0;
   const bool atomic_rank = lane_order_ok();
-  const int sh = shape_for_rank(n, atomic_rank);
+  const int sh = shape_used(n, atomic_rank);
   const int T = tile_keys(sh);
   const uint32_t ntiles = (uint32_t)((n + T - 1) / T);
+  if (ntiles > L.ntiles) return fail(AP_ERR_INVALID, "workspace sized for a larger tile (shape changed after sizing)");
   const size_t zero_bytes = 256 + align_up(sizeof(uint32_t) * (size_t)kDigits * ntiles * kRadix, 256);
 
   // A1 + A2
   {
     uint32_t g = (uint32_t)std::min<size_t>((n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16),
-                                            (size_t)2 * cus);
+                                            (size_t)cus);
     g = std::max<uint32_t>(g, 1);
     prof_begin(AP_KIND_HIST, s);
     hipLaunchKernelGGL((k_hist_plan<kBits, kHistThreads, hist_lcopies<kBits>()>), dim3(g), dim3(kHistThreads), 0, s,
@@ -284,7 +294,7 @@ static ap_status launch_plan_only(const uint32_t* d_in, uint32_t n, uint32_t* ct
   uint32_t* done = ctl + 5 * 8192 + PL_WORDS;
   const int cus = device_cus();
   uint32_t g = (uint32_t)std::min<size_t>(((size_t)n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16),
-                                          (size_t)2 * cus);
+                                          (size_t)cus);
   g = std::max<uint32_t>(g, 1);
   hipLaunchKernelGGL((k_hist_plan<BITS, kHistThreads, hist_lcopies<BITS>()>), dim3(g), dim3(kHistThreads), 0, s,
                      d_in, n, hist, base,
@@ -490,6 +500,12 @@ int ap_rank_check_state(void) { return lane_order_state(); }
 ap_status ap_set_rank_mode(int mode) {
   if (mode != 0 && mode != 1) return fail(AP_ERR_INVALID, "rank mode must be 0 (auto) or 1 (match)");
   set_rank_mode(mode);
+  return AP_OK;
+}
+
+ap_status ap_set_pass_shape(int shape) {
+  if (shape < -1 || shape > 3) return fail(AP_ERR_INVALID, "shape must be -1 (by size) or 0..3");
+  g_shape_override.store(shape);
   return AP_OK;
 }
 

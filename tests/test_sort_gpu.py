@@ -207,3 +207,17 @@ def test_match_rank_path(dist, n):
         _check(inputs.keyset(dist, n, 21).keys)
     finally:
         binding.ap_set_rank_mode(0)
+
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [70_001, (1 << 20) + 77])
+def test_pass_shapes(shape, n):
+    """Every tile shape gives the oracle's result at sizes with a ragged last tile (the 32K-key
+    tile otherwise runs only from 2^25 keys on)."""
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_pass_shape(shape)
+    try:
+        _check(inputs.keyset("e" if n & 1 else "a", n, 31).keys)
+    finally:
+        binding.ap_set_pass_shape(-1)
