@@ -165,7 +165,7 @@ def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True)
     return res
 
 
-def leg_served(binding, torch, np, inputs, pools_dev, nreq: int, rates):
+def leg_served(binding, torch, np, inputs, pools_dev, nreq: int, rates, alone_min_keys: int = 1 << 16):
     """Poisson trace of nreq requests (sizes log-uniform [2^10, 2^24], distribution and pool
     window by request seed) served by the request server at several offered rates, and the same
     trace as one plain launch per request, FIFO on one stream."""
@@ -198,11 +198,12 @@ def leg_served(binding, torch, np, inputs, pools_dev, nreq: int, rates):
 
     # -- served, open loop at rates relative to the plain capacity; plain FIFO at the same rates
     res["points"] = []
-    with binding.Server(hbm_budget_bytes=64 << 30, num_streams=4, max_batch=256, alone_min_keys=1 << 20) as srv:
+    res["alone_min_keys"] = alone_min_keys
+    with binding.Server(hbm_budget_bytes=64 << 30, num_streams=4, max_batch=256, alone_min_keys=alone_min_keys) as srv:
         for frac in rates:
             lam = frac * plain_cap
             tr = inputs.request_trace(nreq, rate_per_s=lam, pool_keys=pool_keys, seed=0)
-            srv.stats(reset_latencies=True)
+            st0 = srv.stats(reset_latencies=True)
             tickets = [0] * nreq
             t0 = time.perf_counter()
             for i, r in enumerate(tr):
@@ -239,7 +240,8 @@ def leg_served(binding, torch, np, inputs, pools_dev, nreq: int, rates):
                 "offered_frac_of_plain_capacity": frac,
                 "offered_req_s": round(lam, 1),
                 "served": {"gkeys_s": round(sum(r.n for r in tr) / wall / 1e9, 3), "p50_ms": round(stt["p50_us"] / 1e3, 4),
-                           "p99_ms": round(stt["p99_us"] / 1e3, 4), "batches": stt["batches"], "alone": stt["alone"]},
+                           "p99_ms": round(stt["p99_us"] / 1e3, 4), "batches": stt["batches"] - st0["batches"],
+                           "alone": stt["alone"] - st0["alone"]},
                 "plain_fifo": {"gkeys_s": round(sum(r.n for r in tr) / wall_p / 1e9, 3),
                                "p50_ms": round(pct(lat_p, 50), 4), "p99_ms": round(pct(lat_p, 99), 4)},
             })
@@ -259,7 +261,9 @@ def main() -> int:
     ap.add_argument("--no-segmented", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=20000)
-    ap.add_argument("--served-rates", default="0.5,0.9,1.25")
+    ap.add_argument("--served-rates", default="0.5,0.9,1.25,2.0")
+    ap.add_argument("--alone-min-keys", type=int, default=1 << 16,
+                    help="served form: requests with at least this many keys run the device-wide sort alone")
     ap.add_argument("--profile-leg", choices=["segmented", "latency"], default=None,
                     help="run only that leg (for rocprofv3) and print its result")
     ap.add_argument("--copy-calib", action="store_true",
@@ -345,10 +349,14 @@ def main() -> int:
     if not args.no_extra and not args.no_segmented:
         log("segmented 4096-segment batch")
         extra["segmented_4096"] = leg_segmented(binding, torch, np, inputs, steps=5)
-    if not args.no_extra and not args.no_served and len(pools) == 5:
+    if not args.no_extra and not args.no_served:
+        for seed, dist in zip(range(2, 6), "bcde"):
+            if dist not in pools:
+                pools[dist] = upload(inputs.keyset(dist, N_MAIN, seed=seed).keys)
         log("served form")
         rates = [float(x) for x in args.served_rates.split(",") if x]
-        extra["served"] = leg_served(binding, torch, np, inputs, pools, args.served_requests, rates)
+        extra["served"] = leg_served(binding, torch, np, inputs, pools, args.served_requests, rates,
+                                     args.alone_min_keys)
 
     cpu = None
     if not args.no_cpu:

@@ -192,7 +192,9 @@ ap_status ap_load_tuning(const char *path);
  *   num_streams       slots = concurrent batches; default 4.
  *   max_batch         requests per batch; default 256.
  *   max_queue         queued requests before AP_ERR_QUEUE_FULL; default 65536.
- *   alone_min_keys    requests with n >= this run alone; default 2^20.
+ *   alone_min_keys    requests with n >= this run alone; default 2^16 (one
+ *                     workgroup per request is slower than the device-wide
+ *                     sort above that size).
  * Zero fields take the default.
  *
  * ap_server_submit: AP_ERR_INVALID for bad arguments, AP_ERR_BUDGET when the

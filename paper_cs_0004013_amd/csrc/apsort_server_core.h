@@ -68,7 +68,7 @@ struct Config {
   int num_streams = 4;
   int max_batch = 256;
   int max_queue = 1 << 16;
-  size_t alone_min_keys = (size_t)1 << 20;  // requests at least this long run alone (device-wide)
+  size_t alone_min_keys = (size_t)1 << 16;  // requests at least this long run alone (device-wide)
 };
 
 struct Stats {

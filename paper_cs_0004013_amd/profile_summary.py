@@ -8,7 +8,8 @@ Each DIR holds one rocprofv3 run (its *_results.db).  The summary lists the mean
 kernel of the trace run, and for the named kernel the FETCH_SIZE and WRITE_SIZE per dispatch,
 each scaled by the factor that makes the same counter read the known size of a plain 256 MiB
 device copy (the copy-calibration runs), giving HBM bytes per launch.  It records a hash of the
-kernel source so that bench.py can tell whether the counters still describe the current kernel.
+kernel source (--source, default apsort_kernels.h) so that bench.py can tell whether the counters
+still describe the current kernel.
 """
 from __future__ import annotations
 
@@ -60,6 +61,7 @@ def main() -> int:
     ap.add_argument("--out", required=True)
     ap.add_argument("--cmd", default="")
     ap.add_argument("--title", default="")
+    ap.add_argument("--source", default=KERNEL_SRC, help="kernel source file whose hash is recorded")
     args = ap.parse_args()
 
     kt = kernel_times(args.trace)
@@ -71,7 +73,7 @@ def main() -> int:
     w_scale = COPY_BYTES / (w_c * 1024.0)
     fetch_b = f_k * 1024.0 * f_scale
     write_b = w_k * 1024.0 * w_scale
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    sha = hashlib.sha256(open(args.source, "rb").read()).hexdigest()[:16]
     dur = [t for t in kt if args.kernel in t[0]]
     lines = [f"# {args.title or args.kernel} rocprofv3 summary", ""]
     if args.cmd:
@@ -90,6 +92,7 @@ def main() -> int:
               f"fetch_bytes_per_launch: {fetch_b:.0f}",
               f"write_bytes_per_launch: {write_b:.0f}",
               f"hbm_bytes_per_launch: {fetch_b + write_b:.0f}",
+              f"kernel_source: {os.path.relpath(args.source, os.path.dirname(HERE))}",
               f"kernel_source_sha: {sha}", ""]
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
