@@ -10,6 +10,7 @@
 
 #include <stddef.h>
 #include <stdint.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -238,6 +239,9 @@ class Server {
   }
 
   void loop() {
+    // The loop waits in steps of kPollUs while device work is in flight; the default 50 us timer
+    // slack of a Linux thread would stretch every such wait to ~70 us, so it is cut to 1 us.
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     ex_->thread_init();
     std::vector<Request*> batch;
     std::unique_lock<std::mutex> lk(mu_);
@@ -302,7 +306,7 @@ class Server {
       if (stopping_ && pending_.empty() && idle) break;
       if (any_busy) {
         // device work in flight: poll again shortly, or earlier if a request arrives
-        cv_work_.wait_for(lk, std::chrono::microseconds(20));
+        cv_work_.wait_for(lk, std::chrono::microseconds(kPollUs));
       } else if (pending_.empty()) {
         cv_work_.wait(lk, [&] { return stopping_ || !pending_.empty(); });
       }
@@ -320,6 +324,7 @@ class Server {
   uint64_t next_ticket_ = 0;
   bool stopping_ = false;
   bool joined_ = false;
+  static constexpr int kPollUs = 10;  // completion polling interval while work is in flight
   std::thread worker_;
 };
 
