@@ -270,8 +270,9 @@ def main() -> int:
                     help="only run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the sort "
-              "is sized for one device's HBM and has no multi-GPU path", file=sys.stderr)
+        print(f"bench.py: the sort runs on one GPU only (asked for --gpus {args.gpus}); it is sized for one "
+              "device's HBM and has no multi-GPU path",
+              file=sys.stderr)
         return 2
 
     import numpy as np

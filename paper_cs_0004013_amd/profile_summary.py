@@ -77,7 +77,7 @@ def main() -> int:
     dur = [t for t in kt if args.kernel in t[0]]
     lines = [f"# {args.title or args.kernel} rocprofv3 summary", ""]
     if args.cmd:
-        lines += ["Commands (run from the repository root on the GPU box):", "", "```", args.cmd.strip(), "```", ""]
+        lines += ["Commands (run from the repository root on an MI355X):", "", "```", args.cmd.strip(), "```", ""]
     lines += ["## Kernel durations (rocprofv3 --kernel-trace --stats)", "",
               "| kernel | calls | mean us |", "|---|---|---|"]
     for name, calls, avg in kt:
