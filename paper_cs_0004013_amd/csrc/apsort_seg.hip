@@ -26,6 +26,9 @@ static const SegCfg kSegCfgs[] = {
     {4, 4, 8},    // 4: 4-bit digits, 256 threads, 2048-key tiles
     {8, 8, 8},    // 5: 512 threads, 4096-key tiles
     {6, 4, 8},    // 6: 6-bit digits, 256 threads, 2048-key tiles
+    {10, 4, 8},   // 7: 10-bit digits (4 sweeps, 1024 buckets), 256 threads, 2048-key tiles
+    {11, 4, 8},   // 8: 11-bit digits (3 sweeps, 2048 buckets), 256 threads, 2048-key tiles
+    {11, 8, 16},  // 9: 11-bit digits, 512 threads, 8192-key tiles
 };
 constexpr int kNumSegCfgs = sizeof(kSegCfgs) / sizeof(kSegCfgs[0]);
 
@@ -54,14 +57,40 @@ void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uin
     case 4: launch_seg_sort<4, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
     case 5: launch_seg_sort<8, 8, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
     case 6: launch_seg_sort<6, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 7: launch_seg_sort<10, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 8: launch_seg_sort<11, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 9: launch_seg_sort<11, 8, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
     default: launch_seg_sort<8, 8, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
   }
 }
 
 // Resident workgroups per CU of each configuration (LDS and registers allow two workgroups of up
 // to 512 threads, one of 1024), times the CU count, capped by the work.
+// LDS of one workgroup of each configuration (the kernel's only shared object).
+template <int BITS, int WAVES, int IPT>
+constexpr size_t seg_lds() {
+  return sizeof(SegSmem<BITS, WAVES, IPT, seg_lcopies<BITS>()>);
+}
+static size_t seg_cfg_lds(int cfg) {
+  switch (cfg) {
+    case 1: return seg_lds<8, 16, 8>();
+    case 2: return seg_lds<8, 4, 16>();
+    case 3: return seg_lds<8, 4, 8>();
+    case 4: return seg_lds<4, 4, 8>();
+    case 5: return seg_lds<8, 8, 8>();
+    case 6: return seg_lds<6, 4, 8>();
+    case 7: return seg_lds<10, 4, 8>();
+    case 8: return seg_lds<11, 4, 8>();
+    case 9: return seg_lds<11, 8, 16>();
+    default: return seg_lds<8, 8, 16>();
+  }
+}
+
+// Persistent grid: as many workgroups as fit on the device at once (by threads and by the 160 KiB
+// of LDS per CU), at most one per work item.
 int seg_workgroups(int cfg, uint32_t nwork) {
-  const int per_cu = (kSegCfgs[cfg].waves * 64 >= 1024) ? 1 : (kSegCfgs[cfg].waves <= 4 ? 4 : 2);
+  int per_cu = (kSegCfgs[cfg].waves * 64 >= 1024) ? 1 : (kSegCfgs[cfg].waves <= 4 ? 4 : 2);
+  per_cu = std::max(1, std::min(per_cu, (int)((size_t)160 * 1024 / seg_cfg_lds(cfg))));
   return (int)std::max<uint32_t>(1u, std::min<uint32_t>(nwork, (uint32_t)(per_cu * device_cus())));
 }
 

@@ -279,21 +279,32 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
       if (sm.flag[d]) continue;  // uniform across the workgroup
       const int shift = d * BITS;
       for (int b = tid; b < R; b += THREADS) sm.running[b] = sm.base[d * R + b];
+      // The tiles of a segment are swept in order by this one workgroup, so the next tile is
+      // known: its loads are issued as soon as the current tile's keys are in LDS and complete
+      // while the current tile is written out.
+      uint32_t k[IPT];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const uint32_t idx = lb0 + j * 64;
+        k[j] = idx < len ? src[idx] : 0xFFFFFFFFu;
+      }
 #pragma unroll 1
       for (uint32_t t = 0; t < ntile; ++t) {
         const uint32_t tb = t * (uint32_t)T;
-        uint32_t k[IPT], r[IPT];
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const uint32_t idx = tb + lb0 + j * 64;
-          k[j] = idx < len ? src[idx] : 0xFFFFFFFFu;
-        }
+        uint32_t r[IPT];
         seg_rank_tile<BITS, WAVES, IPT, LCOPIES>(sm, k, r, shift);
         uint32_t* cnt = sm.u.p.cnt + wid * R;
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
           const uint32_t v = (k[j] >> shift) & (R - 1);
           sm.u.p.stage[cnt[v] + r[j]] = k[j];
+        }
+        if (t + 1 < ntile) {
+#pragma unroll
+          for (int j = 0; j < IPT; ++j) {
+            const uint32_t idx = tb + (uint32_t)T + lb0 + j * 64;
+            k[j] = idx < len ? src[idx] : 0xFFFFFFFFu;
+          }
         }
         __syncthreads();
         const uint32_t nvalid = (len - tb) < (uint32_t)T ? (len - tb) : (uint32_t)T;

@@ -64,7 +64,16 @@ def test_group_split_table():
         binding.set_segmented_groups(saved)
 
 
-@pytest.mark.parametrize("cfg", range(7))
+N_CONFIGS = 10  # compiled-in configurations (digit widths 4, 6, 8, 10, 11)
+
+
+def test_config_count():
+    from paper_cs_0004013_amd import binding
+    assert binding.ap_segmented_num_configs() == N_CONFIGS
+    assert sorted({binding.ap_segmented_config_info(c)[0] for c in range(N_CONFIGS)}) == [4, 6, 8, 10, 11]
+
+
+@pytest.mark.parametrize("cfg", range(N_CONFIGS))
 def test_every_config(cfg):
     L = inputs.segment_lengths(96, seed=cfg + 1, lo=2, hi=1 << 16)
     L[::7] = 0
