@@ -221,3 +221,33 @@ def test_pass_shapes(shape, n):
         _check(inputs.keyset("e" if n & 1 else "a", n, 31).keys)
     finally:
         binding.ap_set_pass_shape(-1)
+
+
+def test_workspace_sort_graph_capture_replay():
+    """ap_sort_u32_ws allocates nothing and never synchronises, so it can be captured in a HIP
+    graph; every replay (with eager work and synchronisation in between) must give the oracle's
+    result for the input then in the buffer."""
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    n = (1 << 20) + 333
+    announce(f"graph capture of the workspace sort n={n}")
+    ws = torch.empty(binding.ap_sort_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    binding.ap_workspace_init(ws)
+    t_in = torch.zeros(n, dtype=torch.int32, device="cuda")
+    t_out = torch.empty_like(t_in)
+    spl = torch.empty(63, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        binding.ap_sort_u32_ws(t_in, t_out, 64, spl, ws, stream=s)
+    for rep, dist in enumerate(["a", "e", "c", "d", "a"]):
+        keys = inputs.keyset(dist, n, 40 + rep).keys
+        t_in.copy_(to_dev(keys)[0])        # eager work between replays
+        t_out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        want = oracle.sort_u32(keys)
+        assert np.array_equal(to_host(t_out), want), f"replay {rep}"
+        assert np.array_equal(to_host(spl), oracle.splitters(want, 64)), f"replay {rep} splitters"
