@@ -1,19 +1,24 @@
 """Autotuner of the segmented sort: picks the kernel configuration (digit width, waves per
 workgroup, keys per lane) of each length group by measurement.
 
-For each length group (a range of floor(log2(segment length)) classes) a synthetic batch whose
-lengths all fall in that group is built (log-uniform lengths, distributions (a)-(e) by segment
-seed, about 2^25 keys in total).  With the group table reduced to that one group, every compiled-in
-configuration sorts the batch (input restored before each run; HIP events on the sort's stream),
-and the configuration with the lowest median time is kept.  The result is written as a table of
-lines "group cls_lo cls_hi cfg" that the library reads with ap_load_tuning.
+The length groups are fixed ranges of floor(log2(segment length)) classes: >= 32K keys, 8K..32K-1,
+2K..8K-1 and 2..2047.  The tuning batch has the workload's shape: 4096 segments with lengths
+log-uniform in [64, 2^18] and distributions (a)-(e) by segment seed; three such batches are
+drawn with seeds of their own (not the benchmark's), because which configuration wins depends on
+the particular lengths (the longest segments set the critical path).  The groups are tuned by
+coordinate descent: for one group at a time, every compiled-in configuration is tried with the
+other groups' choices fixed, scored by the sum over the batches of the median of `reps` runs
+(input restored before each run, HIP events on the sort's stream); the lowest score is kept, and
+the sweep over the groups is repeated `rounds` times.  (Tuning each group on
+a batch of its own lengths alone picks differently: it misses how many segments of each length
+the workload has, and with it how much parallelism each group's kernel gets.)  The result is
+written as lines "group cls_lo cls_hi cfg" that the library reads with ap_load_tuning.
 
-Usage (on the GPU):  python -m paper_cs_0004013_amd.autotune [--out FILE] [--reps R]
+Usage (on the GPU):  python -m paper_cs_0004013_amd.autotune [--out FILE] [--reps R] [--rounds N]
 """
 from __future__ import annotations
 
 import argparse
-import math
 import os
 import sys
 
@@ -21,21 +26,19 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tune_gfx950.txt")
-GROUPS = [(13, 18), (11, 12), (1, 10)]   # >= 8192, 2048..8191, 2..2047 keys (segments up to 2^18 tuned)
-TARGET_KEYS = 1 << 25
+GROUPS = [(15, 31), (13, 14), (11, 12), (1, 10)]   # >= 32K, 8K..32K-1, 2K..8K-1, 2..2047 keys
+START = [1, 1, 5, 3]                                # configurations the descent starts from
+TUNE_SEEDS = (7919, 104729, 1299709)
 
 
-def _batch_for(cls_lo: int, cls_hi: int, seed: int):
+def _batch(seed: int):
     from paper_cs_0004013_amd import inputs
-    lo, hi = 1 << cls_lo, (1 << (cls_hi + 1)) - 1
-    mean = (hi - lo) / max(math.log(hi / lo), 1e-9)
-    nseg = int(min(max(TARGET_KEYS / mean, 64), 65536))
-    L = inputs.segment_lengths(nseg, seed=seed, lo=max(lo, 2), hi=hi)
+    L = inputs.segment_lengths(4096, seed=seed)
     keys, off, _ = inputs.segment_keys(L)
     return keys, off
 
 
-def tune(reps: int = 5, out: str | None = DEFAULT_TABLE, verbose: bool = True) -> list[tuple[int, int, int]]:
+def tune(reps: int = 5, rounds: int = 2, out: str | None = DEFAULT_TABLE, verbose: bool = True):
     import torch
 
     from paper_cs_0004013_amd import binding
@@ -44,45 +47,64 @@ def tune(reps: int = 5, out: str | None = DEFAULT_TABLE, verbose: bool = True) -
     saved = binding.segmented_groups()
     ncfg = binding.ap_segmented_num_configs()
     stream = torch.cuda.Stream()
-    chosen = []
+    batches = [_batch(sd) for sd in TUNE_SEEDS]
+    nkeys = sum(int(k.size) for k, _ in batches)
+    choice = list(START)
     try:
-        for gi, (cls_lo, cls_hi) in enumerate(GROUPS):
-            keys, off = _batch_for(cls_lo, cls_hi, seed=1000 + gi)
-            with torch.cuda.stream(stream):
-                t_src = torch.from_numpy(keys.view(np.int32)).to("cuda")
-                t_work = torch.empty_like(t_src)
-                t_off = torch.from_numpy(off.view(np.int32)).to("cuda")
-                best = None
-                for cfg in range(ncfg):
-                    binding.set_segmented_groups([(cls_lo, cls_hi, cfg)] + [(1, 0, 0)] * (binding.SEG_GROUPS - 1))
+        with torch.cuda.stream(stream):
+            dev = [(torch.from_numpy(k.view(np.int32)).to("cuda"), torch.from_numpy(o.view(np.int32)).to("cuda"))
+                   for k, o in batches]
+            t_work = torch.empty(max(int(k.size) for k, _ in batches), dtype=torch.int32, device="cuda")
+
+            def measure() -> float:
+                binding.set_segmented_groups([(lo, hi, c) for (lo, hi), c in zip(GROUPS, choice)])
+                total = 0.0
+                for t_src, t_off in dev:
+                    work = t_work[:t_src.numel()]
                     times = []
                     for r in range(reps + 1):
-                        t_work.copy_(t_src)
+                        work.copy_(t_src)
                         a = torch.cuda.Event(enable_timing=True)
                         b = torch.cuda.Event(enable_timing=True)
                         a.record(stream)
-                        binding.ap_sort_u32_segmented(t_work, t_off, stream=stream)
+                        binding.ap_sort_u32_segmented(work, t_off, stream=stream)
                         b.record(stream)
                         stream.synchronize()
                         if r:
                             times.append(a.elapsed_time(b))
-                    ms = float(np.median(times))
-                    bits, waves, ipt = binding.ap_segmented_config_info(cfg)
-                    if verbose:
-                        print(f"[tune] group {gi} classes {cls_lo}..{cls_hi} ({keys.size} keys, {off.size - 1} segs) "
-                              f"cfg {cfg} (bits {bits}, waves {waves}, ipt {ipt}): {ms:.3f} ms "
-                              f"{keys.size / ms / 1e6:.1f} Gkeys/s", flush=True)
-                    if best is None or ms < best[0]:
-                        best = (ms, cfg)
-            chosen.append((cls_lo, cls_hi, best[1]))
+                    total += float(np.median(times))
+                return total
+
+            best = measure()
+            if verbose:
+                print(f"[tune] {len(dev)} batches of 4096 segments, {nkeys} keys; start {choice}: {best:.3f} ms",
+                      flush=True)
+            for rnd in range(rounds):
+                for g in range(len(GROUPS)):
+                    for cfg in range(ncfg):
+                        if cfg == choice[g]:
+                            continue
+                        prev = choice[g]
+                        choice[g] = cfg
+                        ms = measure()
+                        if verbose:
+                            bits, waves, ipt = binding.ap_segmented_config_info(cfg)
+                            print(f"[tune] round {rnd} group {g} classes {GROUPS[g][0]}..{GROUPS[g][1]} cfg {cfg} "
+                                  f"(bits {bits}, waves {waves}, ipt {ipt}): {ms:.3f} ms", flush=True)
+                        if ms < best * 0.995:
+                            best = ms
+                        else:
+                            choice[g] = prev
+                if verbose:
+                    print(f"[tune] after round {rnd}: {choice} {best:.3f} ms "
+                          f"({nkeys / best / 1e6:.1f} Gkeys/s)", flush=True)
     finally:
         binding.set_segmented_groups(saved)
-    # the top group also covers lengths beyond the tuned range
-    chosen[0] = (chosen[0][0], 31, chosen[0][2])
+    chosen = [(lo, hi, c) for (lo, hi), c in zip(GROUPS, choice)]
     if out:
         with open(out, "w") as f:
             f.write("# segmented-sort length groups: group cls_lo cls_hi cfg  (floor(log2 length) classes)\n")
-            f.write("# written by paper_cs_0004013_amd.autotune on the GPU it ran on\n")
+            f.write("# written by paper_cs_0004013_amd.autotune (coordinate descent on three 4096-segment batches)\n")
             for g, (lo, hi, cfg) in enumerate(chosen):
                 f.write(f"{g} {lo} {hi} {cfg}\n")
         if verbose:
@@ -94,8 +116,9 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_TABLE)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--rounds", type=int, default=2)
     args = ap.parse_args()
-    tune(args.reps, args.out)
+    tune(args.reps, args.rounds, args.out)
     return 0
 
 

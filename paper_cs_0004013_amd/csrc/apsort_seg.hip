@@ -29,6 +29,8 @@ static const SegCfg kSegCfgs[] = {
     {10, 4, 8},   // 7: 10-bit digits (4 sweeps, 1024 buckets), 256 threads, 2048-key tiles
     {11, 4, 8},   // 8: 11-bit digits (3 sweeps, 2048 buckets), 256 threads, 2048-key tiles
     {11, 8, 16},  // 9: 11-bit digits, 512 threads, 8192-key tiles
+    {8, 16, 16},  // 10: 1024 threads, 16384-key tiles (segments up to 16K keys in one tile)
+    {8, 8, 32},   // 11: 512 threads, 16384-key tiles
 };
 constexpr int kNumSegCfgs = sizeof(kSegCfgs) / sizeof(kSegCfgs[0]);
 
@@ -60,6 +62,8 @@ void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uin
     case 7: launch_seg_sort<10, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
     case 8: launch_seg_sort<11, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
     case 9: launch_seg_sort<11, 8, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 10: launch_seg_sort<8, 16, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+    case 11: launch_seg_sort<8, 8, 32>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
     default: launch_seg_sort<8, 8, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
   }
 }
@@ -82,6 +86,8 @@ static size_t seg_cfg_lds(int cfg) {
     case 7: return seg_lds<10, 4, 8>();
     case 8: return seg_lds<11, 4, 8>();
     case 9: return seg_lds<11, 8, 16>();
+    case 10: return seg_lds<8, 16, 16>();
+    case 11: return seg_lds<8, 8, 32>();
     default: return seg_lds<8, 8, 16>();
   }
 }
@@ -99,10 +105,12 @@ int seg_tile_keys(int cfg) { return kSegCfgs[cfg].waves * 64 * kSegCfgs[cfg].ipt
 void seg_reset(hipStream_t s, SegCtl* ctl) { hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, s, ctl); }
 
 // Length groups: group g sorts the segments whose floor(log2(length)) lies in [cls_lo, cls_hi] with
-// kernel configuration cfg.  Defaults: one-tile and longer segments with 8192-key tiles, short
-// ones with 2048-key tiles; the tuner rewrites the table (ap_segmented_set_group, ap_load_tuning).
+// kernel configuration cfg.  Defaults (the table measured on gfx950 by the tuner): >= 32K keys
+// with 16K-key tiles (1024 threads), 8K..32K-1 with 8K-key tiles (1024 threads), 2K..8K-1 with
+// 4K-key tiles (512 threads), shorter ones with 2K-key tiles (256 threads).  The tuner rewrites
+// the table (ap_segmented_set_group, ap_load_tuning).
 static std::mutex g_grp_mu;
-static SegGroup g_groups[kSegGroups] = {{13, 31, 0}, {11, 12, 0}, {1, 10, 3}, {1, 0, 0}};
+static SegGroup g_groups[kSegGroups] = {{15, 31, 10}, {13, 14, 1}, {11, 12, 5}, {1, 10, 3}};
 static int g_groups_version = 0;  // bumped on every change (invalidates captured graphs)
 
 int seg_groups_version() {
@@ -145,9 +153,25 @@ struct SegEntry {
   int k_nseg;
   const void* k_status;
   int k_cfg;
+  // length groups after the first run on their own streams, forked from and joined back to
+  // `stream` with events (created on first use)
+  hipStream_t aux[kSegGroups];
+  hipEvent_t ev_fork;
+  hipEvent_t ev_join[kSegGroups];
 };
 static std::mutex g_seg_mu;
 static std::vector<SegEntry> g_seg;
+
+static ap_status seg_fork_objects(SegEntry& c) {
+  if (c.ev_fork) return AP_OK;
+  for (int g = 0; g < kSegGroups; ++g) {
+    hipError_t e = hipStreamCreateWithFlags(&c.aux[g], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.ev_join[g], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort: auxiliary stream");
+  }
+  hipError_t e = hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming);
+  return e == hipSuccess ? AP_OK : hip_fail(e, "segmented sort: fork event");
+}
 
 static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out) {
   int dev = 0;
@@ -173,7 +197,7 @@ static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out) {
       if (st != AP_OK) return st;
     }
     *out = &c;
-    return AP_OK;
+    return seg_fork_objects(c);
   }
   SegEntry c{};
   c.dev = dev;
@@ -188,13 +212,14 @@ static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out) {
   }
   g_seg.push_back(c);
   *out = &g_seg.back();
-  return AP_OK;
+  return seg_fork_objects(g_seg.back());
 }
 
 // The launch sequence: classify -> fill -> persistent sort.  No host synchronisation; every grid
 // size is fixed by (nseg, device), so the sequence can be captured once and replayed.
 ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_off, int nseg, uint32_t* d_status,
-                            void* ws, const SegLayout& L, int cfg, hipStream_t s) {
+                            void* ws, const SegLayout& L, int cfg, hipStream_t s, const hipStream_t* aux,
+                            hipEvent_t ev_fork, const hipEvent_t* ev_join) {
   char* w = static_cast<char*>(ws);
   SegCtl* ctl = reinterpret_cast<SegCtl*>(w + L.ctl);
   SegDesc* order = reinterpret_cast<SegDesc*>(w + L.order);
@@ -206,12 +231,30 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
                      d_status);
   hipLaunchKernelGGL(k_seg_fill, dim3(g1), dim3(256), 0, s, d_off, (uint32_t)nseg, (uint32_t)n_total, ctl, d_keys,
                      tmp, order);
+  // One persistent kernel per length group.  The groups sort disjoint segments and take work from
+  // counters of their own, so they run concurrently: the first group (longest segments) on `s`,
+  // the others on auxiliary streams forked after k_seg_fill and joined before the reset.  A
+  // group's workgroups then fill the CUs that another group's tail (its few longest segments)
+  // leaves idle, instead of waiting for that kernel to end.
   SegGroup grp[kSegGroups];
   seg_groups(grp);
+  hipError_t e = hipEventRecord(ev_fork, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
+  bool first = true;
   for (int g = 0; g < kSegGroups; ++g) {
     if (grp[g].cls_lo > grp[g].cls_hi) continue;
-    launch_seg_cfg(grp[g].cfg, dim3(seg_workgroups(grp[g].cfg, (uint32_t)nseg)), s, order, 0u, ~0u, grp[g].cls_lo,
-                   grp[g].cls_hi, g, ctl);
+    const dim3 grid(seg_workgroups(grp[g].cfg, (uint32_t)nseg));
+    if (first) {
+      launch_seg_cfg(grp[g].cfg, grid, s, order, 0u, ~0u, grp[g].cls_lo, grp[g].cls_hi, g, ctl);
+      first = false;
+      continue;
+    }
+    e = hipStreamWaitEvent(aux[g], ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(fork)");
+    launch_seg_cfg(grp[g].cfg, grid, aux[g], order, 0u, ~0u, grp[g].cls_lo, grp[g].cls_hi, g, ctl);
+    e = hipEventRecord(ev_join[g], aux[g]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev_join[g], 0);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort: join");
   }
   seg_reset(s, ctl);
   prof_end(s);
@@ -249,7 +292,8 @@ ap_status ap_sort_u32_segmented(uint32_t* d_keys, size_t n_total, const uint32_t
     if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
   }
   const bool graphable = s != nullptr && cap == hipStreamCaptureStatusNone && !prof_active();
-  if (!graphable) return enqueue_segmented(d_keys, n_total, d_offsets, nseg, d_status, ent->ws, L, cfg, s);
+  if (!graphable) return enqueue_segmented(d_keys, n_total, d_offsets, nseg, d_status, ent->ws, L, cfg, s, ent->aux, ent->ev_fork,
+                                              ent->ev_join);
   const bool same = ent->exec && ent->k_keys == d_keys && ent->k_n == n_total && ent->k_off == d_offsets &&
                     ent->k_nseg == nseg && ent->k_status == d_status && ent->k_cfg == cfg;
   if (!same) {
@@ -259,7 +303,8 @@ ap_status ap_sort_u32_segmented(uint32_t* d_keys, size_t n_total, const uint32_t
     }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    st = enqueue_segmented(d_keys, n_total, d_offsets, nseg, d_status, ent->ws, L, cfg, s);
+    st = enqueue_segmented(d_keys, n_total, d_offsets, nseg, d_status, ent->ws, L, cfg, s, ent->aux, ent->ev_fork,
+                           ent->ev_join);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
     if (st != AP_OK) {
