@@ -51,6 +51,9 @@ def _bind(path: str):
     lib.oracle_slice_starts.argtypes = [ctypes.c_size_t, ctypes.c_int, u64p]
     lib.oracle_splitters.argtypes = [u32p, ctypes.c_size_t, ctypes.c_int, u32p]
     lib.oracle_sort_segmented.argtypes = [u32p, u64p, ctypes.c_int]
+    lib.oracle_bucket_pass_pairs.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_size_t, ctypes.c_int]
+    lib.oracle_bucket_pass_pairs.restype = None
+    lib.oracle_sort_pairs_u32.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_size_t]
     for f in (lib.oracle_digit_hist, lib.oracle_sort_u32, lib.oracle_slice_starts,
               lib.oracle_splitters, lib.oracle_sort_segmented):
         f.restype = ctypes.c_int
@@ -146,3 +149,27 @@ def sort_segmented(keys, offsets) -> np.ndarray:
     if _load().oracle_sort_segmented(_p32(k), _p64(off), nseg) != 0:
         raise ValueError("oracle_sort_segmented: invalid offsets or out of memory")
     return k
+
+
+def bucket_pass_pairs(keys, values, shift: int) -> tuple[np.ndarray, np.ndarray]:
+    """One stable bucketing pass on the keys' 8-bit digit at ``shift``, values moving with keys."""
+    k, v = _u32(keys), _u32(values)
+    if k.size != v.size:
+        raise ValueError("keys and values differ in length")
+    if not 0 <= shift <= 24:
+        raise ValueError("shift must be in [0, 24]")
+    ok, ov = np.empty_like(k), np.empty_like(v)
+    if k.size:
+        _load().oracle_bucket_pass_pairs(_p32(k), _p32(v), _p32(ok), _p32(ov), k.size, shift)
+    return ok, ov
+
+
+def sort_pairs_u32(keys, values) -> tuple[np.ndarray, np.ndarray]:
+    """(keys, values) sorted by key with four stable bucketing passes; equal keys keep input order."""
+    k, v = _u32(keys), _u32(values)
+    if k.size != v.size:
+        raise ValueError("keys and values differ in length")
+    ok, ov = np.empty_like(k), np.empty_like(v)
+    if k.size and _load().oracle_sort_pairs_u32(_p32(k), _p32(v), _p32(ok), _p32(ov), k.size) != 0:
+        raise MemoryError("oracle_sort_pairs_u32 failed")
+    return ok, ov

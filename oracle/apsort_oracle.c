@@ -30,6 +30,11 @@
  *   - oracle_sort_segmented: the same sort applied independently to each
  *     segment [off[s], off[s+1]) of one array (one local sort per cell, the
  *     "Local Sort" phase of Sec. 3.3).
+ *   - oracle_bucket_pass_pairs / oracle_sort_pairs_u32: the same bucketing
+ *     pass and LSD sort with a 32-bit value travelling with every key.  Each
+ *     pass keeps the order of elements with equal digits (Sec. 3.3.1), so
+ *     pairs with equal keys leave in their input order: with values equal to
+ *     input positions, the output values are the stable sorting permutation.
  *
  * Keys are unsigned 32-bit integers ordered as unsigned values (the paper sorts
  * positive integers; keys with bit 31 set are accepted as well).
@@ -87,6 +92,31 @@ void oracle_bucket_pass(const uint32_t *src, uint32_t *dst, size_t n, int shift)
     }
 }
 
+/* The bucketing pass above with a value moved together with each key: the
+ * cumulative totals give the first slot of each bucket, then element j (in
+ * input order) takes the next free slot of its bucket, its value with it. */
+void oracle_bucket_pass_pairs(const uint32_t *src_k, const uint32_t *src_v,
+                              uint32_t *dst_k, uint32_t *dst_v, size_t n, int shift)
+{
+    uint64_t first[ORACLE_BUCKETS];
+    for (unsigned b = 0; b < ORACLE_BUCKETS; ++b)
+        first[b] = 0;
+    for (size_t j = 0; j < n; ++j)
+        first[(src_k[j] >> shift) & (ORACLE_BUCKETS - 1)] += 1;
+    uint64_t total = 0;
+    for (unsigned b = 0; b < ORACLE_BUCKETS; ++b) {
+        uint64_t c = first[b];
+        first[b] = total;
+        total += c;
+    }
+    for (size_t j = 0; j < n; ++j) {
+        unsigned b = (src_k[j] >> shift) & (ORACLE_BUCKETS - 1);
+        uint64_t slot = first[b]++;
+        dst_k[slot] = src_k[j];
+        dst_v[slot] = src_v[j];
+    }
+}
+
 /* Sec. 3.3.1: LSD radix sort, low-order digit first, four 8-bit digits. */
 int oracle_sort_u32(const uint32_t *in, uint32_t *out, size_t n)
 {
@@ -111,6 +141,32 @@ int oracle_sort_u32(const uint32_t *in, uint32_t *out, size_t n)
     memcpy(out, a, n * sizeof(uint32_t));
     free(a);
     free(b);
+    return 0;
+}
+
+/* Sec. 3.3.1 for (key, value) pairs: four stable bucketing passes on the
+ * keys' 8-bit digits, low digit first, every value moving with its key. */
+int oracle_sort_pairs_u32(const uint32_t *in_k, const uint32_t *in_v,
+                          uint32_t *out_k, uint32_t *out_v, size_t n)
+{
+    if (n == 0)
+        return 0;
+    if (!in_k || !in_v || !out_k || !out_v)
+        return -1;
+    uint32_t *buf = (uint32_t *)malloc(4 * n * sizeof(uint32_t));
+    if (!buf)
+        return -1;
+    /* two (keys, values) buffers; pass d reads buffer d % 2 and writes the other */
+    uint32_t *keys[2] = {buf, buf + 2 * n};
+    uint32_t *vals[2] = {buf + n, buf + 3 * n};
+    memcpy(keys[0], in_k, n * sizeof(uint32_t));
+    memcpy(vals[0], in_v, n * sizeof(uint32_t));
+    for (int d = 0; d < 4; ++d)
+        oracle_bucket_pass_pairs(keys[d % 2], vals[d % 2], keys[(d + 1) % 2], vals[(d + 1) % 2], n,
+                                 d * ORACLE_DIGIT_BITS);
+    memcpy(out_k, keys[0], n * sizeof(uint32_t));  /* after four passes: buffer 0 */
+    memcpy(out_v, vals[0], n * sizeof(uint32_t));
+    free(buf);
     return 0;
 }
 

@@ -181,3 +181,51 @@ def test_invalid_arguments():
         oracle.slice_starts(10, 0)
     with pytest.raises(ValueError):
         oracle.sort_segmented(np.zeros(4, np.uint32), np.array([0, 3, 2], np.uint64))
+
+
+# ---- (key, value) pairs: stability is observable ----------------------------------------------
+
+def test_pairs_exhaustive_tiny_domain():
+    """All key sequences of length 0..4 over six boundary values, values = input positions, against
+    Python's sorted() on (key, position) pairs ordered by key (a stable sort)."""
+    vals6 = BOUNDARY[:6]
+    for L in range(5):
+        for s in itertools.product(vals6, repeat=L):
+            k = np.array(s, dtype=np.uint32)
+            pos = np.arange(L, dtype=np.uint32)
+            ok, ov = oracle.sort_pairs_u32(k, pos)
+            want = sorted(zip(s, range(L)), key=lambda p: p[0])
+            assert ok.tolist() == [p[0] for p in want] and ov.tolist() == [p[1] for p in want], s
+
+
+@pytest.mark.parametrize("dist", inputs.DISTS)
+def test_pairs_values_are_stable_argsort(dist):
+    """With values = positions the output values are numpy's stable argsort (many equal keys in
+    (c) and (e)); arbitrary values follow their keys."""
+    ks = inputs.keyset(dist, 70_001, seed=13)
+    pos = np.arange(ks.keys.size, dtype=np.uint32)
+    ok, ov = oracle.sort_pairs_u32(ks.keys, pos)
+    perm = np.argsort(ks.keys, kind="stable")
+    assert np.array_equal(ov, perm.astype(np.uint32))
+    assert np.array_equal(ok, ks.keys[perm])
+    payload = (pos * np.uint32(2654435761)) ^ np.uint32(0x5BD1E995)
+    ok2, ov2 = oracle.sort_pairs_u32(ks.keys, payload)
+    assert np.array_equal(ok2, ok) and np.array_equal(ov2, payload[perm])
+
+
+@pytest.mark.parametrize("shift", [0, 8, 16, 24])
+def test_pairs_bucket_pass_is_stable_digit_sort(shift):
+    rng = np.random.default_rng(shift + 5)
+    k = rng.integers(0, 1 << 32, size=9_999, dtype=np.uint64).astype(np.uint32)
+    v = rng.integers(0, 1 << 32, size=9_999, dtype=np.uint64).astype(np.uint32)
+    ok, ov = oracle.bucket_pass_pairs(k, v, shift)
+    perm = np.argsort((k >> np.uint32(shift)) & np.uint32(255), kind="stable")
+    assert np.array_equal(ok, k[perm]) and np.array_equal(ov, v[perm])
+
+
+def test_pairs_keys_match_key_sort():
+    rng = np.random.default_rng(99)
+    k = rng.integers(0, 1 << 32, size=123_457, dtype=np.uint64).astype(np.uint32)
+    v = rng.integers(0, 1 << 32, size=k.size, dtype=np.uint64).astype(np.uint32)
+    ok, _ = oracle.sort_pairs_u32(k, v)
+    assert np.array_equal(ok, oracle.sort_u32(k))

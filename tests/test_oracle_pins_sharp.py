@@ -33,6 +33,11 @@ MUTANTS = {
     "histogram digit off by one bit": ("hist[(keys[i] >> shift) & mask] += 1;",
                                        "hist[(keys[i] >> (shift + 1)) & mask] += 1;"),
     "empty cell not padded": (": 0xFFFFFFFFu;", ": 0u;"),
+    "pairs: value left in place": ("dst_v[slot] = src_v[j];", "dst_v[j] = src_v[j];"),
+    "pairs: value of the mirrored element": ("dst_v[slot] = src_v[j];", "dst_v[slot] = src_v[n - 1 - j];"),
+    "pairs: ties reversed": ("    for (size_t j = 0; j < n; ++j) {\n        unsigned b",
+                             "    for (size_t j = n; j-- > 0;) {\n        unsigned b"),
+    "pairs: only three digit passes": ("for (int d = 0; d < 4; ++d)", "for (int d = 0; d < 3; ++d)"),
 }
 
 
@@ -52,6 +57,12 @@ def _battery() -> bool:
         for n in (1, 5, 1000):
             pins.test_closed_forms(n)
         pins.test_segmented_vs_per_segment_numpy()
+        pins.test_pairs_exhaustive_tiny_domain()
+        for dist in ("a", "c", "e"):
+            pins.test_pairs_values_are_stable_argsort(dist)
+        for shift in (0, 16):
+            pins.test_pairs_bucket_pass_is_stable_digit_sort(shift)
+        pins.test_pairs_keys_match_key_sort()
     except AssertionError:
         return False
     return True

@@ -64,7 +64,7 @@ def test_group_split_table():
         binding.set_segmented_groups(saved)
 
 
-N_CONFIGS = 10  # compiled-in configurations (digit widths 4, 6, 8, 10, 11)
+N_CONFIGS = 12  # compiled-in configurations (digit widths 4, 6, 8, 10, 11)
 
 
 def test_config_count():
