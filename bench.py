@@ -107,6 +107,35 @@ def leg_latency(binding, torch, np, inputs):
             "gkeys_s_p50": round((1 << 20) / pct(ms, 50) / 1e6, 2)}
 
 
+def leg_pairs(binding, torch, np, inputs, t_keys, steps: int = 10):
+    """(key, value) pairs: the same 2^26 uniform keys with values 0..n-1 (an argsort); per-pass
+    time from HIP events, 16 algorithmic bytes per key per pass (key and value, read and write)."""
+    n = t_keys.numel()
+    vals = torch.arange(n, dtype=torch.int32, device="cuda")
+    k_out = torch.empty_like(t_keys)
+    v_out = torch.empty_like(vals)
+    for _ in range(3):
+        binding.ap_sort_pairs_u32(t_keys, vals, k_out, v_out, 64, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        binding.ap_sort_pairs_u32(t_keys, vals, k_out, v_out, 64, None)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    binding.ap_profile_read()
+    binding.ap_profile_enable(True)
+    for _ in range(steps):
+        binding.ap_sort_pairs_u32(t_keys, vals, k_out, v_out, 64, None)
+    torch.cuda.synchronize()
+    binding.ap_profile_enable(False)
+    ms, cnt = binding.ap_profile_read()
+    npass = sum(cnt[binding.AP_KIND_PASS + d] for d in range(4))
+    pass_us = sum(ms[binding.AP_KIND_PASS + d] for d in range(4)) / max(npass, 1) * 1e3
+    return {"n": n, "ms_per_sort": round(dt * 1e3, 4), "gpairs_s": round(n / dt / 1e9, 3),
+            "pass_us": round(pass_us, 2), "pass_gbs": round(16 * n / pass_us / 1e3, 1),
+            "pass_frac_of_8tbs": round(16 * n / pass_us / 1e3 / HBM_PEAK_GBS, 4)}
+
+
 def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True):
     """4096 segments, lengths log-uniform in [64, 2^18] (seed 0); segment s uses seed s."""
     L = inputs.segment_lengths(4096, seed=0)
@@ -378,6 +407,8 @@ def main() -> int:
         extra["adversarial_2p27_gkeys_s"] = round((1 << 27) * 5 / d3 / 1e9, 3)
         del k3, o3
     if not args.no_extra:
+        log("pairs 2^26")
+        extra["pairs_2p26"] = leg_pairs(binding, torch, np, inputs, t_in)
         log("latency 2^20")
         extra["latency_2p20"] = leg_latency(binding, torch, np, inputs)
     if not args.no_extra and not args.no_segmented:

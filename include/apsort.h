@@ -103,6 +103,39 @@ ap_status ap_sort_u32_ws(const uint32_t *d_in, uint32_t *d_out, size_t n, int P,
                          void *stream);
 
 /*
+ * ap_sort_pairs_u32 -- sort (key, value) pairs by key.
+ *
+ * The same LSD radix sort on the keys (Sec. 3.2 bucketing per digit, Sec.
+ * 3.3.1 digit order), every 32-bit value moving with its key.  Every pass
+ * keeps the order of elements with equal digits (Sec. 3.3.1), so pairs with
+ * equal keys leave in their input order: with values 0..n-1 the output values
+ * are the stable sorting permutation (an argsort).  The keys, cells and
+ * splitters are exactly those of ap_sort_u32 on d_keys_in.
+ *   d_keys_in, d_vals_in    n keys and n values (never written unless in place)
+ *   d_keys_out, d_vals_out  n sorted keys and their values
+ * In place is allowed when d_keys_in == d_keys_out and d_vals_in ==
+ * d_vals_out (both, or neither: AP_ERR_INVALID otherwise); a key array must
+ * not overlap a value array.  Tiles are at most 16K keys (keys and values are
+ * both staged in LDS).  Scratch (about 8n bytes plus the scan state) comes
+ * from the same per-stream cache as ap_sort_u32.
+ */
+ap_status ap_sort_pairs_u32(const uint32_t *d_keys_in, const uint32_t *d_vals_in,
+                            uint32_t *d_keys_out, uint32_t *d_vals_out, size_t n,
+                            int P, uint32_t *d_splitters, void *stream);
+
+/*
+ * ap_sort_pairs_workspace_bytes / ap_sort_pairs_u32_ws -- the pairs sort with
+ * a caller-owned workspace (prepared once by ap_workspace_init, 256-byte
+ * aligned, at least ap_sort_pairs_workspace_bytes(n) bytes); no allocation,
+ * no host synchronisation.  Returns 0 bytes when n >= AP_MAX_KEYS.
+ */
+size_t ap_sort_pairs_workspace_bytes(size_t n);
+ap_status ap_sort_pairs_u32_ws(const uint32_t *d_keys_in, const uint32_t *d_vals_in,
+                               uint32_t *d_keys_out, uint32_t *d_vals_out, size_t n,
+                               int P, uint32_t *d_splitters, void *d_ws,
+                               size_t ws_bytes, void *stream);
+
+/*
  * ap_digit_plan_u32 -- the first step of the sort on its own, for inspection:
  * the bucket counts of every digit (Sec. 3.2, first loop of bucket()) and the
  * pass plan derived from them.

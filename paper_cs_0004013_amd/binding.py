@@ -37,6 +37,9 @@ SIGNATURES = [
     ("ap_sort_workspace_bytes", _SZ, [_SZ]),
     ("ap_workspace_init", _I, [_VP, _SZ, _VP]),
     ("ap_sort_u32_ws", _I, [_VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
+    ("ap_sort_pairs_u32", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP]),
+    ("ap_sort_pairs_workspace_bytes", _SZ, [_SZ]),
+    ("ap_sort_pairs_u32_ws", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
     ("ap_digit_plan_u32", _I, [_VP, _SZ, _I, _VP, _VP, _VP]),
     ("ap_release_cache", _I, []),
     ("ap_profile_enable", _I, [_I]),
@@ -153,6 +156,49 @@ def ap_sort_u32(t_in, t_out, P: int = 64, t_splitters=None, stream=None) -> None
     st = lib().ap_sort_u32(_keys_ptr(t_in, "in") if n else None, _keys_ptr(t_out, "out") if n else None, n, P,
                            spl or None, _stream(stream))
     check(st, "ap_sort_u32")
+
+
+def ap_sort_pairs_u32(t_keys_in, t_vals_in, t_keys_out, t_vals_out, P: int = 1, t_splitters=None,
+                      stream=None) -> None:
+    """Sort (key, value) pairs by key; pairs with equal keys keep their input order."""
+    n = t_keys_in.numel()
+    for t in (t_vals_in, t_keys_out, t_vals_out):
+        if t.numel() != n:
+            raise ValueError("key and value tensors differ in size")
+    spl = None
+    if t_splitters is not None:
+        if t_splitters.numel() < max(P - 1, 0):
+            raise ValueError("splitter tensor needs P-1 entries")
+        spl = _keys_ptr(t_splitters, "splitters")
+    ptrs = [_keys_ptr(t, name) if n else None for t, name in
+            ((t_keys_in, "keys_in"), (t_vals_in, "vals_in"), (t_keys_out, "keys_out"), (t_vals_out, "vals_out"))]
+    check(lib().ap_sort_pairs_u32(*ptrs, n, P, spl, _stream(stream)), "ap_sort_pairs_u32")
+
+
+def ap_sort_pairs_workspace_bytes(n: int) -> int:
+    return int(lib().ap_sort_pairs_workspace_bytes(n))
+
+
+def ap_sort_pairs_u32_ws(t_keys_in, t_vals_in, t_keys_out, t_vals_out, P: int, t_splitters, t_ws,
+                         stream=None) -> None:
+    n = t_keys_in.numel()
+    spl = _keys_ptr(t_splitters, "splitters") if t_splitters is not None else None
+    ptrs = [_keys_ptr(t, name) if n else None for t, name in
+            ((t_keys_in, "keys_in"), (t_vals_in, "vals_in"), (t_keys_out, "keys_out"), (t_vals_out, "vals_out"))]
+    check(lib().ap_sort_pairs_u32_ws(*ptrs, n, P, spl, t_ws.data_ptr(), t_ws.numel() * t_ws.element_size(),
+                                     _stream(stream)), "ap_sort_pairs_u32_ws")
+
+
+def argsort_u32(t_keys, stream=None):
+    """(sorted keys, stable sorting permutation) of a uint32-bit int32 tensor, via the pairs sort
+    with values 0..n-1."""
+    import torch
+    n = t_keys.numel()
+    idx = torch.arange(n, dtype=torch.int32, device=t_keys.device)
+    k_out = torch.empty_like(t_keys)
+    perm = torch.empty_like(idx)
+    ap_sort_pairs_u32(t_keys, idx, k_out, perm, 1, None, stream)
+    return k_out, perm
 
 
 def ap_sort_workspace_bytes(n: int) -> int:

@@ -170,14 +170,18 @@ constexpr int hist_lcopies() {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Pairs (key + value) stage the values beside the keys in LDS, so their tile is at most 16K keys.
+static int shape_for_pairs(size_t n) { return std::min(shape_used(n, true), 2); }
+
 // Workspace layout (bytes from the 256-byte aligned base):
 //   [hist copies*D*R u32][base D*R u32][plan 32 u32][done 1 u32 | pad][tile counters 8 u32 | pad]
-//   [status D * ntiles * R u32][tmp n u32]
+//   [status D * ntiles * R u32][tmp n u32][pairs only: value tmp n u32]
 // hist and done are self-clearing; tile counters and the used part of status are cleared by
 // k_hist_plan.  Status capacity covers the smaller tile of either rank primitive.
-Layout layout_for(size_t n) {
+Layout layout_for(size_t n, bool pairs) {
   Layout L{};
-  const int T = std::min(tile_keys(shape_used(n, true)), tile_keys(shape_used(n, false)));
+  const int T = pairs ? tile_keys(std::min(shape_for_pairs(n), shape_used(n, false)))
+                      : std::min(tile_keys(shape_used(n, true)), tile_keys(shape_used(n, false)));
   L.tile_keys = T;
   L.ntiles = (uint32_t)((n + T - 1) / T);
   size_t off = 0;
@@ -189,29 +193,31 @@ Layout layout_for(size_t n) {
   L.status = off; off += align_up(sizeof(uint32_t) * (size_t)kDigits * L.ntiles * kRadix, 256);
   L.zero_bytes = off - L.tctr;  // upper bound of the region k_hist_plan clears
   L.tmp = off;    off += align_up(sizeof(uint32_t) * n, 256);
+  L.vtmp = off;
+  if (pairs) off += align_up(sizeof(uint32_t) * n, 256);
   L.total = off;
   L.init_bytes = L.tctr;        // hist, base, plan, done: zeroed once at workspace creation
   return L;
 }
 
-template <int W, int I>
+template <int W, int I, bool KV>
 static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out, uint32_t* tmp,
                         uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d, uint32_t* st_d,
-                        uint32_t* tctr) {
+                        uint32_t* tctr, const uint32_t* vin, uint32_t* vout, uint32_t* vtmp) {
   if constexpr (W * 64 * I <= 16384) {
     if (!atomic_rank) {
-      hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d, plan,
-                         base_d, st_d, tctr);
+      hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH, 4, KV>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d,
+                         plan, base_d, st_d, tctr, vin, vout, vtmp);
       return;
     }
   }
-  hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_ATOMIC>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d, plan, base_d,
-                     st_d, tctr);
+  hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_ATOMIC, 4, KV>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d, plan,
+                     base_d, st_d, tctr, vin, vout, vtmp);
 }
 
 // ---------------------------------------------------------------- launch sequence
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl,
-                       void* ws, const Layout& L, hipStream_t s) {
+                       void* ws, const Layout& L, hipStream_t s, const uint32_t* d_vin, uint32_t* d_vout) {
   char* w = static_cast<char*>(ws);
   uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
   uint32_t* base = reinterpret_cast<uint32_t*>(w + L.base);
@@ -220,11 +226,13 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
   uint32_t* tctr = reinterpret_cast<uint32_t*>(w + L.tctr);
   uint32_t* status = reinterpret_cast<uint32_t*>(w + L.status);
   uint32_t* tmp = reinterpret_cast<uint32_t*>(w + L.tmp);
+  const bool pairs = d_vout != nullptr;
+  uint32_t* vtmp = pairs ? reinterpret_cast<uint32_t*>(w + L.vtmp) : nullptr;
   const uint32_t nn = (uint32_t)n;
   const int cus = device_cus();
   const int inplace = (d_in == d_out) ? 1 : 0;
   const bool atomic_rank = lane_order_ok();
-  const int sh = shape_used(n, atomic_rank);
+  const int sh = pairs ? std::min(shape_for_pairs(n), shape_used(n, atomic_rank)) : shape_used(n, atomic_rank);
   const int T = tile_keys(sh);
   const uint32_t ntiles = (uint32_t)((n + T - 1) / T);
   if (ntiles > L.ntiles) return fail(AP_ERR_INVALID, "workspace sized for a larger tile (shape changed after sizing)");
@@ -250,24 +258,36 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
     const uint32_t* base_d = base + d * kRadix;
     prof_begin(AP_KIND_PASS + d, s);
     const dim3 grid(ntiles);
-    switch (sh) {
-      case 3: launch_pass<16, 32>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
-      case 2: launch_pass<8, 32>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
-      case 1: launch_pass<4, 16>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
-      default: launch_pass<4, 8>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr); break;
+#define APS_PASS(W, I, KV)                                                                                    \
+  launch_pass<W, I, KV>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr, d_vin, d_vout, \
+                        vtmp)
+    if (pairs) {
+      switch (sh) {
+        case 2: APS_PASS(8, 32, true); break;
+        case 1: APS_PASS(4, 16, true); break;
+        default: APS_PASS(4, 8, true); break;
+      }
+    } else {
+      switch (sh) {
+        case 3: APS_PASS(16, 32, false); break;
+        case 2: APS_PASS(8, 32, false); break;
+        case 1: APS_PASS(4, 16, false); break;
+        default: APS_PASS(4, 8, false); break;
+      }
     }
+#undef APS_PASS
     prof_end(s);
     ap_status st = check_launch(s, "k_pass");
     if (st != AP_OK) return st;
   }
   // A7
   {
-    const size_t work = std::max<size_t>(n / 4, (size_t)P);
+    const size_t work = std::max<size_t>((pairs ? n / 2 : n / 4), (size_t)P);
     uint32_t g = (uint32_t)std::min<size_t>((work + 255 * 8) / (256 * 8), (size_t)4 * cus);
     g = std::max<uint32_t>(g, 1);
     prof_begin(AP_KIND_FINAL, s);
     hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, d_in, d_out, tmp, nn, plan, (uint32_t)P,
-                       P > 1 ? d_spl : nullptr);
+                       P > 1 ? d_spl : nullptr, d_vin, d_vout, vtmp);
     prof_end(s);
     ap_status st = check_launch(s, "k_finalize");
     if (st != AP_OK) return st;
@@ -360,6 +380,31 @@ ap_status check_sort_args(const uint32_t* d_in, const uint32_t* d_out, size_t n,
     if (a0 < b1 && b0 < a1) return fail(AP_ERR_INVALID, "input and output overlap without being equal");
   }
   return AP_OK;
+}
+
+// Pairs: the keys' rules for the values, both arrays in place or neither, and no key array
+// overlapping a value array.
+static ap_status check_pairs_args(const uint32_t* kin, const uint32_t* vin, const uint32_t* kout,
+                                  const uint32_t* vout, size_t n, int P) {
+  ap_status st = check_sort_args(kin, kout, n, P);
+  if (st == AP_OK) st = check_sort_args(vin, vout, n, P);
+  if (st != AP_OK || n == 0) return st;
+  if ((kin == kout) != (vin == vout))
+    return fail(AP_ERR_INVALID, "keys and values must both be sorted in place or both out of place");
+  const uintptr_t ks[2] = {(uintptr_t)kin, (uintptr_t)kout}, vs[2] = {(uintptr_t)vin, (uintptr_t)vout};
+  for (uintptr_t a : ks)
+    for (uintptr_t b : vs)
+      if (a < b + n * 4 && b < a + n * 4) return fail(AP_ERR_INVALID, "a key array overlaps a value array");
+  return AP_OK;
+}
+
+static ap_status pairs_with_ws(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, size_t n,
+                               int P, uint32_t* d_spl, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (n == 0) return P > 1 && d_spl ? fill_u32(d_spl, 0xFFFFFFFFu, (size_t)P - 1, s) : AP_OK;
+  const Layout L = layout_for(n, true);
+  if (!ws || ws_bytes < L.total) return fail(AP_ERR_INVALID, "workspace too small: %zu < %zu", ws_bytes, L.total);
+  if ((uintptr_t)ws & 255u) return fail(AP_ERR_INVALID, "workspace must be 256-byte aligned");
+  return enqueue_sort(kin, kout, n, P, d_spl, ws, L, s, vin, vout);
 }
 
 ap_status sort_with_ws(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
@@ -481,6 +526,33 @@ ap_status ap_sort_u32_ws(const uint32_t* d_in, uint32_t* d_out, size_t n, int P,
   ap_status st = check_sort_args(d_in, d_out, n, P);
   if (st != AP_OK) return st;
   return sort_with_ws(d_in, d_out, n, P, d_splitters, d_ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+size_t ap_sort_pairs_workspace_bytes(size_t n) {
+  if (n >= AP_MAX_KEYS) return 0;
+  return layout_for(n, true).total;
+}
+
+ap_status ap_sort_pairs_u32(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_t* d_keys_out,
+                            uint32_t* d_vals_out, size_t n, int P, uint32_t* d_splitters, void* stream) {
+  ap_status st = check_pairs_args(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, P);
+  if (st != AP_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) return pairs_with_ws(nullptr, nullptr, nullptr, nullptr, 0, P, d_splitters, nullptr, 0, s);
+  const Layout L = layout_for(n, true);
+  void* ws = nullptr;
+  st = cached_workspace(L.total, s, &ws);
+  if (st != AP_OK) return st;
+  return enqueue_sort(d_keys_in, d_keys_out, n, P, d_splitters, ws, L, s, d_vals_in, d_vals_out);
+}
+
+ap_status ap_sort_pairs_u32_ws(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_t* d_keys_out,
+                               uint32_t* d_vals_out, size_t n, int P, uint32_t* d_splitters, void* d_ws,
+                               size_t ws_bytes, void* stream) {
+  ap_status st = check_pairs_args(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, P);
+  if (st != AP_OK) return st;
+  return pairs_with_ws(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, P, d_splitters, d_ws, ws_bytes,
+                       static_cast<hipStream_t>(stream));
 }
 
 ap_status ap_digit_plan_u32(const uint32_t* d_in, size_t n, int digit_bits, uint32_t* d_hist, uint32_t* d_plan,

@@ -11,14 +11,14 @@ namespace aps {
 
 // Byte offsets of the single-array sort workspace (see layout_for).
 struct Layout {
-  size_t hist, base, plan, done, tctr, status, tmp, total;
+  size_t hist, base, plan, done, tctr, status, tmp, vtmp, total;
   size_t zero_bytes;  // bytes from tctr that k_hist_plan clears on every call
   size_t init_bytes;  // bytes from 0 that must be zero before the first call
   uint32_t ntiles;
   int tile_keys;
 };
 
-Layout layout_for(size_t n);
+Layout layout_for(size_t n, bool pairs = false);
 
 ap_status fail(ap_status st, const char* fmt, ...);
 ap_status hip_fail(hipError_t e, const char* what);
@@ -44,8 +44,10 @@ int seg_workgroups(int cfg, uint32_t nwork);
 int seg_tile_keys(int cfg);
 void seg_groups(SegGroup* out);  // kSegGroups entries
 void seg_reset(hipStream_t s, SegCtl* ctl);
+// d_vout != nullptr: (key, value) pairs, the values read from d_vin and written to d_vout
+// (workspace from layout_for(n, true)).
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
-                       const Layout& L, hipStream_t s);
+                       const Layout& L, hipStream_t s, const uint32_t* d_vin = nullptr, uint32_t* d_vout = nullptr);
 
 ap_status enqueue_digit_plan(const uint32_t* d_in, size_t n, int bits, uint32_t* d_hist, uint32_t* d_plan,
                              hipStream_t s);

@@ -201,11 +201,12 @@ __global__ __launch_bounds__(256) void k_lane_order_probe(uint32_t* __restrict__
 // look-back); load; rank; publish the tile's bucket counts; tile-local scan; reorder the keys in
 // LDS; look back for the global bucket starts; write the reordered keys out.
 // ------------------------------------------------------------------------------------------------
-template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN = 4>
+template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN = 4, bool KV = false>
 __global__ __launch_bounds__(WAVES * 64) void k_pass(
     const uint32_t* in, uint32_t* out, uint32_t* tmp, uint32_t n, int d,
     const uint32_t* __restrict__ plan, const uint32_t* __restrict__ g_base,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ tile_ctr) {
+    uint32_t* __restrict__ status, uint32_t* __restrict__ tile_ctr, const uint32_t* vin, uint32_t* vout,
+    uint32_t* vtmp) {
   constexpr int R = 1 << BITS;
   constexpr int THREADS = WAVES * 64;
   constexpr int T = THREADS * IPT;
@@ -214,12 +215,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   const uint32_t ssel = plan[PL_SRC + d], dsel = plan[PL_DST + d];
   const uint32_t* __restrict__ src = ssel == SEL_IN ? in : (ssel == SEL_OUT ? out : tmp);
   uint32_t* __restrict__ dst = dsel == SEL_OUT ? out : tmp;
+  // values (pairs only) live in the matching buffers and move exactly as their keys
+  const uint32_t* __restrict__ vsrc = ssel == SEL_IN ? vin : (ssel == SEL_OUT ? vout : vtmp);
+  uint32_t* __restrict__ vdst = dsel == SEL_OUT ? vout : vtmp;
   const int shift = d * BITS;
 
   __shared__ uint32_t s_cnt[WAVES * R];  // per-wave bucket counters, then per-wave run starts
   __shared__ uint32_t s_lbase[R + 1];    // tile-local bucket starts (+ tile size)
   __shared__ uint32_t s_delta[R];        // global start minus tile-local start, per bucket
   __shared__ uint32_t s_stage[T];        // keys in tile-sorted order
+  __shared__ uint32_t s_vstage[KV ? T : 1];  // their values (pairs)
   __shared__ uint32_t s_scan[WAVES];
   __shared__ uint32_t s_tile;
   __shared__ uint64_t s_bins[RANK == RANK_MATCH ? WAVES * R : 1];  // per-wave bucket lane masks
@@ -236,15 +241,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
 
   // ---- load: keys past n become all-ones sentinels (largest digit, last in order) ----
   uint32_t k[IPT];
+  uint32_t val[KV ? IPT : 1];
   const uint32_t wbase = tbase + (uint32_t)(wid * 64 * IPT + lane);
   if (tbase + (uint32_t)T <= n) {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) k[j] = src[wbase + j * 64];
+    if constexpr (KV) {
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) val[j] = vsrc[wbase + j * 64];
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const uint32_t idx = wbase + j * 64;
       k[j] = idx < n ? src[idx] : 0xFFFFFFFFu;
+      if constexpr (KV) val[j] = idx < n ? vsrc[idx] : 0u;
     }
   }
 
@@ -299,6 +310,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   for (int j = 0; j < IPT; ++j) {
     const uint32_t v = (k[j] >> shift) & (R - 1);
     s_stage[cnt_w[v] + r[j]] = k[j];
+    if constexpr (KV) s_vstage[cnt_w[v] + r[j]] = val[j];
   }
 
   // ---- A3: decoupled look-back for each bucket's global start ----
@@ -352,6 +364,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
       const uint32_t key = s_stage[i];
       const uint32_t v = (key >> shift) & (R - 1);
       dst[s_delta[v] + i] = key;
+      if constexpr (KV) vdst[s_delta[v] + i] = s_vstage[i];
     }
   }
 }
@@ -360,22 +373,30 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
 // A7: output contract.  Copies the sorted keys into the output when no pass wrote it, and writes
 // splitter p-1 = first key of cell p (all-ones for an empty cell).
 // ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void copy_u32(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, size_t n,
+                                         size_t gtid, size_t gstride) {
+  if ((((uintptr_t)src | (uintptr_t)dst) & 15u) == 0u) {
+    const uint4* __restrict__ s = reinterpret_cast<const uint4*>(src);
+    uint4* __restrict__ o = reinterpret_cast<uint4*>(dst);
+    const size_t nv = n >> 2;
+    for (size_t i = gtid; i < nv; i += gstride) o[i] = s[i];
+    for (size_t i = nv * 4 + gtid; i < n; i += gstride) dst[i] = src[i];
+  } else {
+    for (size_t i = gtid; i < n; i += gstride) dst[i] = src[i];
+  }
+}
+
+// vout != nullptr: pairs; their values are copied along with the keys.
 __global__ void k_finalize(const uint32_t* in, uint32_t* out, const uint32_t* tmp, uint32_t n,
-                           const uint32_t* __restrict__ plan, uint32_t P, uint32_t* __restrict__ splitters) {
+                           const uint32_t* __restrict__ plan, uint32_t P, uint32_t* __restrict__ splitters,
+                           const uint32_t* vin, uint32_t* vout, const uint32_t* vtmp) {
   const uint32_t fsel = plan[PL_FINAL];
   const uint32_t* __restrict__ fin = fsel == SEL_IN ? in : (fsel == SEL_OUT ? out : tmp);
   const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t gstride = (size_t)gridDim.x * blockDim.x;
   if (plan[PL_COPY]) {
-    if ((((uintptr_t)fin | (uintptr_t)out) & 15u) == 0u) {
-      const uint4* __restrict__ s = reinterpret_cast<const uint4*>(fin);
-      uint4* __restrict__ o = reinterpret_cast<uint4*>(out);
-      const size_t nv = n >> 2;
-      for (size_t i = gtid; i < nv; i += gstride) o[i] = s[i];
-      for (size_t i = nv * 4 + gtid; i < n; i += gstride) out[i] = fin[i];
-    } else {
-      for (size_t i = gtid; i < n; i += gstride) out[i] = fin[i];
-    }
+    copy_u32(fin, out, n, gtid, gstride);
+    if (vout) copy_u32(fsel == SEL_IN ? vin : (fsel == SEL_OUT ? vout : vtmp), vout, n, gtid, gstride);
   }
   if (splitters) {
     const uint64_t q = n / P, r = n % P;

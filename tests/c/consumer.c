@@ -77,6 +77,35 @@ int main(void) {
   CHECK_HIP(hipMemcpy(got, d_out, n * 4, hipMemcpyDeviceToHost));
   if (memcmp(got, want, n * 4) != 0) { fprintf(stderr, "in-place workspace sort differs\n"); return 1; }
 
+  /* pairs: values = positions, i.e. an argsort; equal keys keep their input order */
+  {
+    uint32_t *d_vin = NULL, *d_vout = NULL;
+    uint32_t* hv = (uint32_t*)malloc(n * 4);
+    for (size_t i = 0; i < n; ++i) {
+      h[i] &= 0xFFFFu; /* many equal keys: the order among them is observable */
+      hv[i] = (uint32_t)i;
+    }
+    CHECK_HIP(hipMalloc((void**)&d_vin, n * 4));
+    CHECK_HIP(hipMalloc((void**)&d_vout, n * 4));
+    CHECK_HIP(hipMemcpy(d_in, h, n * 4, hipMemcpyHostToDevice));
+    CHECK_HIP(hipMemcpy(d_vin, hv, n * 4, hipMemcpyHostToDevice));
+    CHECK_AP(ap_sort_pairs_u32(d_in, d_vin, d_out, d_vout, n, 1, NULL, NULL));
+    CHECK_HIP(hipDeviceSynchronize());
+    CHECK_HIP(hipMemcpy(got, d_out, n * 4, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(hv, d_vout, n * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; ++i) {
+      if (got[i] != h[hv[i]]) { fprintf(stderr, "pairs: value %zu does not belong to its key\n", i); return 1; }
+      if (i && (got[i - 1] > got[i] || (got[i - 1] == got[i] && hv[i - 1] >= hv[i]))) {
+        fprintf(stderr, "pairs: order or stability broken at %zu\n", i);
+        return 1;
+      }
+    }
+    for (size_t i = 0; i < n; ++i) h[i] = rnd31(); /* restore a full-range key set */
+    hipFree(d_vin);
+    hipFree(d_vout);
+    free(hv);
+  }
+
   /* segmented: 7 segments in place */
   uint32_t off[8] = {0, 5, 5, 70000, 70001, 400000, 1234567, (uint32_t)n};
   CHECK_HIP(hipMalloc((void**)&d_off, sizeof off));

@@ -1,0 +1,130 @@
+"""Parity of the (key, value) pairs sort with the CPU oracle, through the C ABI.
+
+The oracle's pairs sort is stable (equal keys keep their input order), so with values equal to
+input positions the expected values are the unique stable sorting permutation: the comparison
+is bit-exact for keys, values and splitters."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_cs_0004013_amd import inputs
+from tests.gpu_util import announce, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _pairs(keys: np.ndarray, vals: np.ndarray, P: int = 64, inplace: bool = False):
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    announce(f"pairs n={keys.size} P={P} inplace={inplace}")
+    k_in, _kb = to_dev(keys)
+    v_in, _vb = to_dev(vals)
+    if inplace:
+        k_out, v_out = k_in, v_in
+    else:
+        k_out, _ = to_dev(np.zeros(keys.size, np.uint32))
+        v_out, _ = to_dev(np.zeros(keys.size, np.uint32))
+    spl = torch.empty(max(P - 1, 1), dtype=torch.int32, device="cuda")
+    binding.ap_sort_pairs_u32(k_in, v_in, k_out, v_out, P, spl)
+    torch.cuda.synchronize()
+    return to_host(k_out), to_host(v_out), to_host(spl)[:max(P - 1, 0)]
+
+
+def _check(keys: np.ndarray, vals: np.ndarray | None = None, P: int = 64, inplace: bool = False):
+    if vals is None:
+        vals = np.arange(keys.size, dtype=np.uint32)
+    gk, gv, gs = _pairs(keys, vals, P, inplace)
+    wk, wv = oracle.sort_pairs_u32(keys, vals)
+    bad = np.flatnonzero((gk != wk) | (gv != wv))
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+    assert np.array_equal(gs, oracle.splitters(wk, P))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 2047, 2048, 2049, 70_001, (1 << 20) + 7, (1 << 22) + 77])
+def test_sizes(n):
+    _check(inputs.keyset("e", n, seed=n % 97).keys)
+
+
+@pytest.mark.parametrize("dist", inputs.DISTS)
+def test_distributions_with_payload(dist):
+    ks = inputs.keyset(dist, (1 << 21) + 333, seed=17)
+    pos = np.arange(ks.keys.size, dtype=np.uint32)
+    _check(ks.keys, (pos * np.uint32(2654435761)) ^ np.uint32(0xC2B2AE35))
+
+
+def test_full_size_clustered_keys():
+    """2^26 keys of distribution (e): at most ~4096 distinct values, so nearly every key has
+    thousands of equal keys and the stable order of their values is fully observable."""
+    _check(inputs.keyset("e", 1 << 26, seed=5).keys)
+
+
+@pytest.mark.parametrize("n", [1000, (1 << 20) + 3])
+def test_in_place(n):
+    _check(inputs.keyset("d", n, seed=3).keys, inplace=True)
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_every_tile_shape(shape):
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_pass_shape(shape)
+    try:
+        _check(inputs.keyset("a", 300_007, seed=shape).keys)
+    finally:
+        binding.ap_set_pass_shape(-1)
+
+
+def test_mask_rank_path():
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_rank_mode(1)
+    try:
+        _check(inputs.keyset("e", (1 << 22) + 5, seed=2).keys)
+    finally:
+        binding.ap_set_rank_mode(0)
+
+
+def test_argsort_helper():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    keys = inputs.keyset("c", 100_000, seed=1).keys ^ (np.arange(100_000, dtype=np.uint32) % 7)
+    t, _ = to_dev(keys)
+    k_out, perm = binding.argsort_u32(t)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(perm), np.argsort(keys, kind="stable").astype(np.uint32))
+    assert np.array_equal(to_host(k_out), np.sort(keys))
+
+
+def test_invalid_arguments():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    a = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    b = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    c = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    with pytest.raises(binding.ApError):
+        binding.ap_sort_pairs_u32(a, b, a, c)      # keys in place, values not
+    with pytest.raises(binding.ApError):
+        binding.ap_sort_pairs_u32(a, b, c, a)      # value output overlaps the key input
+    big = torch.zeros(2000, dtype=torch.int32, device="cuda")
+    with pytest.raises(binding.ApError):
+        binding.ap_sort_pairs_u32(big[:1000], big[500:1500], c, b)  # key and value inputs overlap
+
+
+def test_workspace_variant():
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    keys = inputs.keyset("b", 500_001, seed=9).keys
+    vals = np.arange(keys.size, dtype=np.uint32)[::-1].copy()
+    ws = torch.empty(binding.ap_sort_pairs_workspace_bytes(keys.size), dtype=torch.uint8, device="cuda")
+    binding.ap_workspace_init(ws)
+    k_in, _ = to_dev(keys)
+    v_in, _ = to_dev(vals)
+    k_out = torch.empty_like(k_in)
+    v_out = torch.empty_like(v_in)
+    spl = torch.empty(63, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        binding.ap_sort_pairs_u32_ws(k_in, v_in, k_out, v_out, 64, spl, ws)
+        torch.cuda.synchronize()
+        wk, wv = oracle.sort_pairs_u32(keys, vals)
+        assert np.array_equal(to_host(k_out), wk) and np.array_equal(to_host(v_out), wv)
+        assert np.array_equal(to_host(spl), oracle.splitters(wk, 64))
