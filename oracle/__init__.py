@@ -54,6 +54,7 @@ def _bind(path: str):
     lib.oracle_bucket_pass_pairs.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_size_t, ctypes.c_int]
     lib.oracle_bucket_pass_pairs.restype = None
     lib.oracle_sort_pairs_u32.argtypes = [u32p, u32p, u32p, u32p, ctypes.c_size_t]
+    lib.oracle_merge_u32.argtypes = [u32p, ctypes.c_size_t, u32p, ctypes.c_size_t, u32p]
     for f in (lib.oracle_digit_hist, lib.oracle_sort_u32, lib.oracle_slice_starts,
               lib.oracle_splitters, lib.oracle_sort_segmented):
         f.restype = ctypes.c_int
@@ -173,3 +174,13 @@ def sort_pairs_u32(keys, values) -> tuple[np.ndarray, np.ndarray]:
     if k.size and _load().oracle_sort_pairs_u32(_p32(k), _p32(v), _p32(ok), _p32(ov), k.size) != 0:
         raise MemoryError("oracle_sort_pairs_u32 failed")
     return ok, ov
+
+
+def merge_u32(a, b) -> np.ndarray:
+    """Merge of two nondecreasing key arrays (Sec. 3.4 / 4.6 merge step); ties take ``a`` first."""
+    x, y = _u32(a), _u32(b)
+    out = np.empty(x.size + y.size, dtype=np.uint32)
+    if out.size and _load().oracle_merge_u32(_p32(x) if x.size else None, x.size,
+                                             _p32(y) if y.size else None, y.size, _p32(out)) != 0:
+        raise ValueError("oracle_merge_u32: invalid argument")
+    return out

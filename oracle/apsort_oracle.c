@@ -30,6 +30,12 @@
  *   - oracle_sort_segmented: the same sort applied independently to each
  *     segment [off[s], off[s+1]) of one array (one local sort per cell, the
  *     "Local Sort" phase of Sec. 3.3).
+ *   - oracle_merge_u32: the merge step of the merge-exchange (Sec. 3.4: two
+ *     sorted lists merged "in the classic manner"; Sec. 4.6: two sorted runs of
+ *     one array merged): repeatedly move the smaller head element to the
+ *     output, the first list's element on a tie.  Splitting the merged list at
+ *     the first list's length gives the merge-exchange: the lower cell keeps
+ *     the lower values, both cells keep their element counts.
  *   - oracle_bucket_pass_pairs / oracle_sort_pairs_u32: the same bucketing
  *     pass and LSD sort with a 32-bit value travelling with every key.  Each
  *     pass keeps the order of elements with equal digits (Sec. 3.3.1), so
@@ -167,6 +173,26 @@ int oracle_sort_pairs_u32(const uint32_t *in_k, const uint32_t *in_v,
     memcpy(out_k, keys[0], n * sizeof(uint32_t));  /* after four passes: buffer 0 */
     memcpy(out_v, vals[0], n * sizeof(uint32_t));
     free(buf);
+    return 0;
+}
+
+/* Sec. 3.4 / 4.6: merge of two nondecreasing lists; ties take the first list's
+ * element first.  out must not overlap a or b. */
+int oracle_merge_u32(const uint32_t *a, size_t na, const uint32_t *b, size_t nb, uint32_t *out)
+{
+    if ((na && !a) || (nb && !b) || ((na + nb) && !out))
+        return -1;
+    size_t i = 0, j = 0, k = 0;
+    while (i < na && j < nb) {
+        if (b[j] < a[i])
+            out[k++] = b[j++];
+        else
+            out[k++] = a[i++];
+    }
+    while (i < na)
+        out[k++] = a[i++];
+    while (j < nb)
+        out[k++] = b[j++];
     return 0;
 }
 

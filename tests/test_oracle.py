@@ -229,3 +229,36 @@ def test_pairs_keys_match_key_sort():
     v = rng.integers(0, 1 << 32, size=k.size, dtype=np.uint64).astype(np.uint32)
     ok, _ = oracle.sort_pairs_u32(k, v)
     assert np.array_equal(ok, oracle.sort_u32(k))
+
+
+# ---- merge of two sorted runs (merge-exchange, Sec. 3.4 / 4.6) ---------------------------------
+
+def test_merge_exhaustive_tiny_domain():
+    """Every pair of nondecreasing sequences of length 0..3 over six boundary values, against
+    sorted() of the concatenation."""
+    vals6 = sorted(BOUNDARY[:6])
+    seqs = [list(s) for L in range(4) for s in itertools.combinations_with_replacement(vals6, L)]
+    for a in seqs:
+        for b in seqs:
+            got = oracle.merge_u32(np.array(a, np.uint32), np.array(b, np.uint32))
+            assert got.tolist() == sorted(a + b), (a, b)
+
+
+@pytest.mark.parametrize("na,nb", [(0, 0), (0, 7), (9, 0), (1, 1), (1000, 3), (3, 1000), (70_001, 65_536),
+                                   (1 << 18, (1 << 18) + 11)])
+def test_merge_vs_numpy(na, nb):
+    rng = np.random.default_rng(na * 31 + nb)
+    a = np.sort(rng.integers(0, 1 << 32, size=na, dtype=np.uint64).astype(np.uint32))
+    b = np.sort(rng.integers(0, 1 << 20, size=nb, dtype=np.uint64).astype(np.uint32) * np.uint32(4096))
+    assert np.array_equal(oracle.merge_u32(a, b), np.sort(np.concatenate([a, b])))
+
+
+def test_merge_closed_forms():
+    a = np.arange(0, 200, 2, dtype=np.uint32)
+    b = np.arange(1, 200, 2, dtype=np.uint32)
+    assert np.array_equal(oracle.merge_u32(a, b), np.arange(200, dtype=np.uint32))   # interleave
+    lo = np.arange(50, dtype=np.uint32)
+    hi = np.arange(50, 90, dtype=np.uint32)
+    assert np.array_equal(oracle.merge_u32(hi, lo), np.arange(90, dtype=np.uint32))  # b entirely first
+    eq = np.full(33, 7, np.uint32)
+    assert np.array_equal(oracle.merge_u32(eq, eq[:5]), np.full(38, 7, np.uint32))

@@ -38,6 +38,9 @@ MUTANTS = {
     "pairs: ties reversed": ("    for (size_t j = 0; j < n; ++j) {\n        unsigned b",
                              "    for (size_t j = n; j-- > 0;) {\n        unsigned b"),
     "pairs: only three digit passes": ("for (int d = 0; d < 4; ++d)", "for (int d = 0; d < 3; ++d)"),
+    "merge: rest of the second list dropped": ("    while (j < nb)\n        out[k++] = b[j++];", "    while (j + 1 < nb)\n        out[k++] = b[j++];"),
+    "merge: compares against the previous head": ("if (b[j] < a[i])", "if (j > 0 && b[j - 1] < a[i])"),
+    "merge: takes the larger head": ("if (b[j] < a[i])", "if (b[j] > a[i])"),
 }
 
 
@@ -63,6 +66,10 @@ def _battery() -> bool:
         for shift in (0, 16):
             pins.test_pairs_bucket_pass_is_stable_digit_sort(shift)
         pins.test_pairs_keys_match_key_sort()
+        pins.test_merge_exhaustive_tiny_domain()
+        for na, nb in ((1000, 3), (70_001, 65_536)):
+            pins.test_merge_vs_numpy(na, nb)
+        pins.test_merge_closed_forms()
     except AssertionError:
         return False
     return True
