@@ -136,6 +136,28 @@ def leg_pairs(binding, torch, np, inputs, t_keys, steps: int = 10):
             "pass_frac_of_8tbs": round(16 * n / pass_us / 1e3 / HBM_PEAK_GBS, 4)}
 
 
+def leg_merge(binding, torch, np, inputs, t_keys, steps: int = 10):
+    """Merge of two sorted runs of 2^25 keys each (the sorted halves of the 2^26 uniform keys):
+    8 algorithmic bytes per output key (read once, written once)."""
+    n = t_keys.numel()
+    a = torch.sort(t_keys[: n // 2])[0]
+    b = torch.sort(t_keys[n // 2:])[0]
+    out = torch.empty_like(t_keys)
+    for _ in range(3):
+        binding.ap_merge_u32(a, b, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        binding.ap_merge_u32(a, b, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ok = bool(torch.equal(out, torch.sort(t_keys)[0]))
+    return {"n": n, "ms": round(ms, 4), "gkeys_s": round(n / ms / 1e6, 2), "gbs": round(8 * n / ms / 1e6, 1),
+            "frac_of_8tbs": round(8 * n / ms / 1e6 / HBM_PEAK_GBS, 4), "ok": ok}
+
+
 def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True):
     """4096 segments, lengths log-uniform in [64, 2^18] (seed 0); segment s uses seed s."""
     L = inputs.segment_lengths(4096, seed=0)
@@ -407,6 +429,8 @@ def main() -> int:
         extra["adversarial_2p27_gkeys_s"] = round((1 << 27) * 5 / d3 / 1e9, 3)
         del k3, o3
     if not args.no_extra:
+        log("merge 2 x 2^25")
+        extra["merge_2x2p25"] = leg_merge(binding, torch, np, inputs, t_in)
         log("pairs 2^26")
         extra["pairs_2p26"] = leg_pairs(binding, torch, np, inputs, t_in)
         log("latency 2^20")

@@ -136,6 +136,31 @@ ap_status ap_sort_pairs_u32_ws(const uint32_t *d_keys_in, const uint32_t *d_vals
                                size_t ws_bytes, void *stream);
 
 /*
+ * ap_merge_u32 -- merge two sorted runs: the merge step of the merge-exchange
+ * (Sec. 3.4: two sorted lists merged in the classic manner; the cell with the
+ * lower id keeps the lower values).
+ *   d_a, na   keys in nondecreasing order (unsigned)
+ *   d_b, nb   keys in nondecreasing order
+ *   d_out     na + nb keys: the merged, nondecreasing sequence; equal keys
+ *             from d_a come before those from d_b.  d_out[0..na) and
+ *             d_out[na..na+nb) are the two cells' parts after a merge-exchange.
+ * na + nb < 2^30; d_out must not overlap an input (AP_ERR_INVALID).  Inputs that
+ * are not sorted give an unspecified permutation of the keys (nothing outside
+ * d_out is written).  Scratch (one word per 4096 outputs) comes from a
+ * per-stream cache.
+ */
+ap_status ap_merge_u32(const uint32_t *d_a, size_t na, const uint32_t *d_b,
+                       size_t nb, uint32_t *d_out, void *stream);
+
+/*
+ * ap_merge_adjacent_u32 -- merge the sorted runs d_keys[0..na) and
+ * d_keys[na..na+nb) of one array in place (Sec. 4.6: the two sorted lists of
+ * one cell's array merged into one).  The runs are copied to per-stream
+ * scratch (4(na+nb) bytes) and merged back.
+ */
+ap_status ap_merge_adjacent_u32(uint32_t *d_keys, size_t na, size_t nb, void *stream);
+
+/*
  * ap_digit_plan_u32 -- the first step of the sort on its own, for inspection:
  * the bucket counts of every digit (Sec. 3.2, first loop of bucket()) and the
  * pass plan derived from them.
@@ -290,10 +315,10 @@ ap_status ap_release_cache(void);
  * events, adds each launch's duration to its kind, returns the totals and
  * clears them.  Kinds: AP_KIND_HIST (bucket counts + plan), AP_KIND_PASS + d
  * (digit pass d, d = 0..7; a pass the plan skips still records its near-empty
- * launch), AP_KIND_FINAL (copy + splitters), AP_KIND_SEG (segmented-sort
+ * launch), AP_KIND_FINAL (copy + splitters), AP_KIND_MERGE (ap_merge_*), AP_KIND_SEG (segmented-sort
  * kernels).  ms and launches have at least AP_NKINDS entries.
  */
-enum { AP_KIND_HIST = 0, AP_KIND_PASS = 1, AP_KIND_FINAL = 9, AP_KIND_SEG = 10, AP_NKINDS = 16 };
+enum { AP_KIND_HIST = 0, AP_KIND_PASS = 1, AP_KIND_FINAL = 9, AP_KIND_SEG = 10, AP_KIND_MERGE = 11, AP_NKINDS = 16 };
 ap_status ap_profile_enable(int on);
 ap_status ap_profile_read(double *ms, uint64_t *launches, int nkinds);
 

@@ -40,6 +40,8 @@ SIGNATURES = [
     ("ap_sort_pairs_u32", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP]),
     ("ap_sort_pairs_workspace_bytes", _SZ, [_SZ]),
     ("ap_sort_pairs_u32_ws", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
+    ("ap_merge_u32", _I, [_VP, _SZ, _VP, _SZ, _VP, _VP]),
+    ("ap_merge_adjacent_u32", _I, [_VP, _SZ, _SZ, _VP]),
     ("ap_digit_plan_u32", _I, [_VP, _SZ, _I, _VP, _VP, _VP]),
     ("ap_release_cache", _I, []),
     ("ap_profile_enable", _I, [_I]),
@@ -201,6 +203,24 @@ def argsort_u32(t_keys, stream=None):
     return k_out, perm
 
 
+def ap_merge_u32(t_a, t_b, t_out, stream=None) -> None:
+    """Merge two sorted runs into t_out (equal keys: t_a's first)."""
+    na, nb = t_a.numel(), t_b.numel()
+    if t_out.numel() != na + nb:
+        raise ValueError("output size must be len(a) + len(b)")
+    check(lib().ap_merge_u32(_keys_ptr(t_a, "a") if na else None, na, _keys_ptr(t_b, "b") if nb else None, nb,
+                             _keys_ptr(t_out, "out") if na + nb else None, _stream(stream)), "ap_merge_u32")
+
+
+def ap_merge_adjacent_u32(t_keys, na: int, stream=None) -> None:
+    """Merge the sorted runs t_keys[:na] and t_keys[na:] in place."""
+    n = t_keys.numel()
+    if not 0 <= na <= n:
+        raise ValueError("na out of range")
+    check(lib().ap_merge_adjacent_u32(_keys_ptr(t_keys, "keys") if n else None, na, n - na, _stream(stream)),
+          "ap_merge_adjacent_u32")
+
+
 def ap_sort_workspace_bytes(n: int) -> int:
     return int(lib().ap_sort_workspace_bytes(n))
 
@@ -231,7 +251,7 @@ def ap_digit_plan_u32(t_in, digit_bits: int, t_hist, t_plan=None, stream=None) -
     check(st, "ap_digit_plan_u32")
 
 
-AP_KIND_HIST, AP_KIND_PASS, AP_KIND_FINAL, AP_KIND_SEG, AP_NKINDS = 0, 1, 9, 10, 16
+AP_KIND_HIST, AP_KIND_PASS, AP_KIND_FINAL, AP_KIND_SEG, AP_KIND_MERGE, AP_NKINDS = 0, 1, 9, 10, 11, 16
 
 
 def ap_profile_enable(on: bool = True) -> None:
