@@ -170,6 +170,16 @@ constexpr int hist_lcopies() {
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Workgroups of k_hist_plan: 16 keys per thread or more, at most one workgroup per CU, but never
+// so few that a thread counts more than kHistMaxVecPerThread vectors of 4 keys (the 16-bit lane
+// copies of the counters would overflow).
+static uint32_t hist_grid(size_t n, int cus) {
+  size_t g = std::min<size_t>((n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16), (size_t)cus);
+  const size_t per_wg_max = (size_t)kHistThreads * 4 * kHistMaxVecPerThread;
+  g = std::max<size_t>(g, (n + per_wg_max - 1) / per_wg_max);
+  return (uint32_t)std::max<size_t>(g, 1);
+}
+
 // Pairs (key + value) stage the values beside the keys in LDS, so their tile is at most 16K keys.
 static int shape_for_pairs(size_t n) { return std::min(shape_used(n, true), 2); }
 
@@ -240,9 +250,7 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
 
   // A1 + A2
   {
-    uint32_t g = (uint32_t)std::min<size_t>((n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16),
-                                            (size_t)cus);
-    g = std::max<uint32_t>(g, 1);
+    const uint32_t g = hist_grid(n, cus);
     prof_begin(AP_KIND_HIST, s);
     hipLaunchKernelGGL((k_hist_plan<kBits, kHistThreads, hist_lcopies<kBits>()>), dim3(g), dim3(kHistThreads), 0, s,
                        d_in, nn,
@@ -313,9 +321,7 @@ static ap_status launch_plan_only(const uint32_t* d_in, uint32_t n, uint32_t* ct
   uint32_t* plan = ctl + 5 * 8192;               // PL_WORDS
   uint32_t* done = ctl + 5 * 8192 + PL_WORDS;
   const int cus = device_cus();
-  uint32_t g = (uint32_t)std::min<size_t>(((size_t)n + (size_t)kHistThreads * 16 - 1) / ((size_t)kHistThreads * 16),
-                                          (size_t)cus);
-  g = std::max<uint32_t>(g, 1);
+  const uint32_t g = hist_grid(n, cus);
   hipLaunchKernelGGL((k_hist_plan<BITS, kHistThreads, hist_lcopies<BITS>()>), dim3(g), dim3(kHistThreads), 0, s,
                      d_in, n, hist, base,
                      plan, done, (uint4*)nullptr, 0u, 0, d_hist, 4u);

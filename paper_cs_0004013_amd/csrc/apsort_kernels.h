@@ -36,10 +36,15 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t coun
 //   done     workgroup-completion counter, zero on entry and on exit
 //   zero_ptr/zero_vec4  scan state of the passes (tile counters + status words), cleared here
 //   out_hist optional copy of the final counts (inspection entry point)
-// Inside a workgroup the counts go to LCOPIES copies in LDS, lane l using copy l % LCOPIES, so that
-// lanes holding equal digits (clustered keys) collide on one LDS word at most 64/LCOPIES-fold.
-// Copies sit HW+1 words apart so that equal buckets of different copies fall in different banks.
+// Inside a workgroup, with 8-bit digits and 1024 threads (1024 counters), every lane position l
+// of the wave owns a private copy of the counters as 16-bit halves: bucket B is the half B & 1 of
+// LDS word (B / 2) * 64 + l, so the 64 lanes of one atomic add always hit 64 different banks
+// (random digits would otherwise collide 4-5 fold per bank).  The 16 waves share the copies,
+// hence the adds stay atomic; a copy counts the keys of 16 threads, at most
+// 16 * (4 * kHistMaxVecPerThread + 2) < 2^16, which the host guarantees through the grid size.
+// Other widths use LCOPIES full-word copies, lane l using copy l % LCOPIES, HW+1 words apart.
 // ------------------------------------------------------------------------------------------------
+constexpr uint32_t kHistMaxVecPerThread = 1023;  // 4-key vectors counted by one thread, at most
 template <int BITS, int THREADS, int LCOPIES>
 __global__ __launch_bounds__(THREADS) void k_hist_plan(
     const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restrict__ g_hist,
@@ -50,21 +55,27 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
   constexpr int D = (32 + BITS - 1) / BITS;
   constexpr int HW = D * R;
   constexpr int CS = HW + 1;  // copy stride
-  __shared__ uint32_t h[LCOPIES * CS];
+  constexpr bool LANE_PRIV = (HW == 1024 && THREADS == 1024);
+  constexpr int HWORDS = LANE_PRIV ? (HW / 2) * 64 : LCOPIES * CS;
+  __shared__ uint32_t h[HWORDS];
   __shared__ uint32_t s_const[kMaxDigits];
   __shared__ uint32_t s_scan[THREADS / 64];
   __shared__ int s_last;
 
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < LCOPIES * CS; i += THREADS) h[i] = 0u;
+  for (uint32_t i = tid; i < (uint32_t)HWORDS; i += THREADS) h[i] = 0u;
   const uint32_t gtid = blockIdx.x * THREADS + tid, gstride = gridDim.x * THREADS;
   for (uint32_t i = gtid; i < zero_vec4; i += gstride) zero_ptr[i] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
 
-  uint32_t* __restrict__ hc = h + (tid % LCOPIES) * CS;
+  uint32_t* __restrict__ hc = LANE_PRIV ? h + (tid & 63u) : h + (tid % LCOPIES) * CS;
   auto count = [&](uint32_t k) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) atomicAdd(&hc[d * R + ((k >> (d * BITS)) & (R - 1))], 1u);
+    for (int d = 0; d < D; ++d) {
+      const uint32_t b = (uint32_t)(d * R) + ((k >> (d * BITS)) & (R - 1));
+      if constexpr (LANE_PRIV) atomicAdd(&hc[(b >> 1) * 64u], 1u << ((b & 1u) * 16u));
+      else atomicAdd(&hc[b], 1u);
+    }
   };
   uint32_t head = (uint32_t)(((16u - ((uintptr_t)keys & 15u)) & 15u) >> 2);
   if (head > n) head = n;
@@ -72,12 +83,36 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
   const uint4* __restrict__ v = reinterpret_cast<const uint4*>(keys + head);
   const uint32_t nv = (n - head) >> 2;
   uint32_t i = gtid;
-  for (; i + 3 * gstride < nv; i += 4 * gstride) {
-    const uint4 a = v[i], b = v[i + gstride], c = v[i + 2 * gstride], e = v[i + 3 * gstride];
-    count(a.x); count(a.y); count(a.z); count(a.w);
-    count(b.x); count(b.y); count(b.z); count(b.w);
-    count(c.x); count(c.y); count(c.z); count(c.w);
-    count(e.x); count(e.y); count(e.z); count(e.w);
+  if (i + 3 * gstride < nv) {
+    // Software pipelined over two register sets: the next four vectors are in flight while the
+    // current four are counted.  rounds = number of r with i + 4*gstride*r + 3*gstride < nv.  The
+    // loop has a fixed trip count and no exit between a load and its use (otherwise the compiler
+    // sinks the loads below the counting); the last round of an even count re-reads the vectors
+    // just loaded (cache hits) instead of branching around the load.
+    const uint32_t step = 4 * gstride;
+    const uint32_t rounds = (nv - 3 * gstride - i + step - 1) / step;
+    auto load4 = [&](uint32_t r, uint4* q) {
+      const uint32_t at = i + r * step;
+      q[0] = v[at];
+      q[1] = v[at + gstride];
+      q[2] = v[at + 2 * gstride];
+      q[3] = v[at + 3 * gstride];
+    };
+    auto count4 = [&](const uint4* q) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { count(q[u].x); count(q[u].y); count(q[u].z); count(q[u].w); }
+    };
+    uint4 qa[4], qb[4];
+    load4(0, qa);
+    uint32_t r = 0;
+    for (; r + 2 <= rounds; r += 2) {  // qa holds round r
+      load4(r + 1, qb);
+      count4(qa);
+      load4(r + 2 < rounds ? r + 2 : r + 1, qa);
+      count4(qb);
+    }
+    if (r < rounds) count4(qa);  // odd count: qa holds the last round
+    i += rounds * step;
   }
   for (; i < nv; i += gstride) {
     const uint4 a = v[i];
@@ -88,8 +123,15 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
   uint32_t* __restrict__ mine = g_hist + (size_t)(blockIdx.x % ncopies) * HW;
   for (uint32_t j = tid; j < HW; j += THREADS) {
     uint32_t c = 0u;
+    if constexpr (LANE_PRIV) {
+      // lane copies read in a rotated order: the 64 lanes of a read hit 64 different banks
+      const uint32_t row = (j >> 1) * 64u, sh = (j & 1u) * 16u;
+#pragma unroll 16
+      for (uint32_t q = 0; q < 64u; ++q) c += (h[row + ((q + j) & 63u)] >> sh) & 0xFFFFu;
+    } else {
 #pragma unroll
-    for (int cp = 0; cp < LCOPIES; ++cp) c += h[cp * CS + j];
+      for (int cp = 0; cp < LCOPIES; ++cp) c += h[cp * CS + j];
+    }
     if (c) add_agent(&mine[j], c);
   }
   // Last-workgroup-done: the barrier makes every thread's adds complete before thread 0's

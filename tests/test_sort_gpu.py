@@ -128,6 +128,53 @@ def test_digit_histograms_and_plan(bits, dist):
     assert plan[D] == sum(run)
 
 
+def test_maximum_size_counts_and_sort():
+    """n = 2^30 - 1, the largest n accepted.  The histogram's workgroups each count up to 4092
+    keys per thread into 16-bit per-lane counters; with constant keys one counter of every copy
+    takes all of them, its worst case.  Then two sorts at that size, checked on the device by
+    properties that hold at any size: a two-valued input by counts, and a uniform input by
+    order (as unsigned), key sum and the top-16-bit histogram."""
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    n = (1 << 30) - 1
+    announce(f"maximum size n={n}: constant-key histogram")
+    t = torch.full((n,), 0x12345678, dtype=torch.int32, device="cuda")
+    h = torch.zeros(4 * 256, dtype=torch.int32, device="cuda")
+    p = torch.zeros(5, dtype=torch.int32, device="cuda")
+    binding.ap_digit_plan_u32(t, 8, h, p)
+    hh = to_host(h).reshape(4, 256)
+    for d in range(4):
+        want = np.zeros(256, np.uint32)
+        want[(0x12345678 >> (8 * d)) & 255] = n
+        assert np.array_equal(hh[d], want), f"digit {d}"
+    assert to_host(p).tolist() == [0, 0, 0, 0, 0]
+    del t
+
+    announce(f"maximum size n={n}: two-valued sort")
+    g = torch.Generator(device="cuda").manual_seed(5)
+    keys = torch.randint(0, 2, (n,), device="cuda", generator=g, dtype=torch.int32)
+    keys.mul_(-8).add_(7)            # 7 or -1 (= 0xFFFFFFFF unsigned)
+    c7 = int((keys == 7).sum())
+    out = torch.empty_like(keys)
+    spl = torch.empty(63, dtype=torch.int32, device="cuda")
+    binding.ap_sort_u32(keys, out, 64, spl)
+    torch.cuda.synchronize()
+    assert bool((out[:c7] == 7).all()) and bool((out[c7:] == -1).all())
+
+    announce(f"maximum size n={n}: uniform sort")
+    keys = torch.randint(-(1 << 31), 1 << 31, (n,), device="cuda", generator=g, dtype=torch.int32)
+    binding.ap_sort_u32(keys, out, 64, spl)
+    torch.cuda.synchronize()
+    flip = out ^ torch.tensor(-(1 << 31), dtype=torch.int32, device="cuda")  # unsigned order as signed
+    assert bool((flip[1:] >= flip[:-1]).all())
+    del flip
+    mask = (1 << 32) - 1
+    assert int((keys.to(torch.int64) & mask).sum()) == int((out.to(torch.int64) & mask).sum())
+    top_in = torch.bincount(((keys >> 16) & 0xFFFF).to(torch.int64), minlength=1 << 16)
+    top_out = torch.bincount(((out >> 16) & 0xFFFF).to(torch.int64), minlength=1 << 16)
+    assert torch.equal(top_in, top_out)
+
+
 def test_pass_skip_counts():
     keys24 = inputs.keyset("a", 100_000, 3).keys >> np.uint32(7)      # < 2^24: 3 passes
     assert _plan(keys24, 8)[1][4] == 3
