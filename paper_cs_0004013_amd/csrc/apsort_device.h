@@ -55,6 +55,26 @@ __device__ __forceinline__ uint64_t match_any(uint32_t v) {
   return m;
 }
 
+// Stable rank of this lane's digit v among the wave's keys ranked so far, against the wave's own
+// LDS counters cnt (one word per digit).  LDS executes one wave's instructions in order and
+// services the conflicting lanes of one instruction in lane order, so the value an atomic
+// increment returns is the number of this wave's earlier keys (earlier instructions, then lower
+// lanes) with the same digit.  Lanes sharing a digit queue on one LDS word, lane by lane; when
+// every lane holds lane 0's digit (runs of equal keys, as earlier passes bring them together),
+// lane 0 adds 64 once and lane l's rank is the old count + l, the same result.  (Ranking slots
+// with a few shared digits by digit leaders measured slower than the atomics on every key set
+// tried.)
+__device__ __forceinline__ uint32_t rank_slot(uint32_t* cnt, uint32_t v) {
+  const uint32_t v0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+  if (__builtin_amdgcn_ballot_w64(v == v0) == ~0ull) {
+    uint32_t old = 0u;
+    if ((threadIdx.x & 63u) == 0u)
+      old = __hip_atomic_fetch_add(&cnt[v0], 64u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return (uint32_t)__builtin_amdgcn_readlane((int)old, 0) + (threadIdx.x & 63u);
+  }
+  return __hip_atomic_fetch_add(&cnt[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // In-place exclusive scan of a[0..N) in LDS by the whole workgroup; returns the total.
 // scratch needs THREADS/64 words.  Starts and ends with a workgroup barrier.
 template <int N, int THREADS>

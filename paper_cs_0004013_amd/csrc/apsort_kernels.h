@@ -305,14 +305,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   uint32_t r[IPT];
   uint32_t* cnt = s_cnt + wid * R;
   if constexpr (RANK == RANK_ATOMIC) {
-    // LDS executes one wave's instructions in order and services the conflicting lanes of one
-    // instruction in lane order, so the value returned to a key is the number of keys of this
-    // wave, earlier in memory order, with the same digit.
+    // lane-ordered LDS atomics (rank_slot), one add of 64 for a slot of one digit
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      const uint32_t v = (k[j] >> shift) & (R - 1);
-      r[j] = __hip_atomic_fetch_add(&cnt[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
+    for (int j = 0; j < IPT; ++j) r[j] = rank_slot(cnt, (k[j] >> shift) & (R - 1));
   } else {
     // Every lane ORs its lane bit into its bucket's 64-bit word, reads the word back (the lanes of
     // this sub-step sharing the bucket) and clears it; the lowest such lane updates the counter.

@@ -144,10 +144,7 @@ __device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>
   __syncthreads();
   uint32_t* cnt = sm.u.p.cnt + wid * R;
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const uint32_t v = (k[j] >> shift) & (R - 1);
-    r[j] = __hip_atomic_fetch_add(&cnt[v], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-  }
+  for (int j = 0; j < IPT; ++j) r[j] = rank_slot(cnt, (k[j] >> shift) & (R - 1));
   tile_bucket_offsets<R, WAVES>(sm.u.p.cnt, sm.lbase, sm.scan);
   for (int b = tid; b < R; b += THREADS) sm.tot[b] = sm.lbase[b + 1] - sm.lbase[b];
   __syncthreads();
