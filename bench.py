@@ -32,12 +32,13 @@ sys.path.insert(0, ROOT)
 METRIC = "Gkeys/s on 64M u32 & 4096-segment batch; % HBM roofline; p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 N_MAIN = 1 << 26
-KERNEL_SRC = os.path.join(ROOT, "paper_cs_0004013_amd", "csrc", "apsort_kernels.h")
+# the pass kernel and the device helpers it inlines (rank, look-back words)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_cs_0004013_amd", "csrc", f) for f in ("apsort_kernels.h", "apsort_device.h")]
 COUNTERS = os.path.join(ROOT, "profiles", "k_pass_counters_uniform_2p26.md")
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRCS)).hexdigest()[:16]
 
 
 def read_traffic():
@@ -333,7 +334,7 @@ def main() -> int:
     ap.add_argument("--served-rates", default="0.5,0.9,1.25,2.0")
     ap.add_argument("--alone-min-keys", type=int, default=1 << 16,
                     help="served form: requests with at least this many keys run the device-wide sort alone")
-    ap.add_argument("--profile-leg", choices=["segmented", "latency"], default=None,
+    ap.add_argument("--profile-leg", choices=["segmented", "latency", "merge"], default=None,
                     help="run only that leg (for rocprofv3) and print its result")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration under rocprofv3)")
@@ -368,6 +369,10 @@ def main() -> int:
         return 0
     if args.profile_leg == "latency":
         print(json.dumps(leg_latency(binding, torch, np, inputs)), flush=True)
+        return 0
+    if args.profile_leg == "merge":
+        t_keys = torch.from_numpy(inputs.keyset("a", N_MAIN, seed=1).keys.view(np.int32)).to("cuda")
+        print(json.dumps(leg_merge(binding, torch, np, inputs, t_keys, steps=3)), flush=True)
         return 0
 
     def upload(keys):

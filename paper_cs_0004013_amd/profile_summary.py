@@ -8,8 +8,8 @@ Each DIR holds one rocprofv3 run (its *_results.db).  The summary lists the mean
 kernel of the trace run, and for the named kernel the FETCH_SIZE and WRITE_SIZE per dispatch,
 each scaled by the factor that makes the same counter read the known size of a plain 256 MiB
 device copy (the copy-calibration runs), giving HBM bytes per launch.  It records a hash of the
-kernel source (--source, default apsort_kernels.h) so that bench.py can tell whether the counters
-still describe the current kernel.
+kernel's sources (--source, comma-separated; default apsort_kernels.h and the device helpers of
+apsort_device.h) so that bench.py can tell whether the counters still describe the current kernel.
 """
 from __future__ import annotations
 
@@ -20,7 +20,7 @@ import os
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = os.path.join(HERE, "csrc", "apsort_kernels.h")
+KERNEL_SRC = ",".join(os.path.join(HERE, "csrc", f) for f in ("apsort_kernels.h", "apsort_device.h"))
 COPY_BYTES = 4 * (1 << 26)
 
 
@@ -61,7 +61,8 @@ def main() -> int:
     ap.add_argument("--out", required=True)
     ap.add_argument("--cmd", default="")
     ap.add_argument("--title", default="")
-    ap.add_argument("--source", default=KERNEL_SRC, help="kernel source file whose hash is recorded")
+    ap.add_argument("--source", default=KERNEL_SRC,
+                    help="kernel source file(s), comma-separated, whose joint hash is recorded")
     args = ap.parse_args()
 
     kt = kernel_times(args.trace)
@@ -73,7 +74,8 @@ def main() -> int:
     w_scale = COPY_BYTES / (w_c * 1024.0)
     fetch_b = f_k * 1024.0 * f_scale
     write_b = w_k * 1024.0 * w_scale
-    sha = hashlib.sha256(open(args.source, "rb").read()).hexdigest()[:16]
+    srcs = [x for x in args.source.split(",") if x]
+    sha = hashlib.sha256(b"".join(open(x, "rb").read() for x in srcs)).hexdigest()[:16]
     dur = [t for t in kt if args.kernel in t[0]]
     lines = [f"# {args.title or args.kernel} rocprofv3 summary", ""]
     if args.cmd:
@@ -92,7 +94,7 @@ def main() -> int:
               f"fetch_bytes_per_launch: {fetch_b:.0f}",
               f"write_bytes_per_launch: {write_b:.0f}",
               f"hbm_bytes_per_launch: {fetch_b + write_b:.0f}",
-              f"kernel_source: {os.path.relpath(args.source, os.path.dirname(HERE))}",
+              "kernel_source: " + ",".join(os.path.relpath(x, os.path.dirname(HERE)) for x in srcs),
               f"kernel_source_sha: {sha}", ""]
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
