@@ -60,6 +60,19 @@ def test_full_size_clustered_keys():
     _check(inputs.keyset("e", 1 << 26, seed=5).keys)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_runs_of_equal_keys(seed):
+    """Runs of equal keys of random lengths 1..199 in input order: one wave's rank slots switch
+    between all-lanes-equal digits (one add of 64) and mixed digits (lane-ordered atomics), in
+    every pass; the values (input positions) must come out as the stable argsort."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(1, 200, size=30_000)
+    vals = rng.integers(0, 1 << 32, size=lens.size, dtype=np.uint64).astype(np.uint32)
+    vals[::3] &= np.uint32(0xFF)              # some runs differ only in the low digit
+    keys = np.repeat(vals, lens)
+    _check(keys)
+
+
 @pytest.mark.parametrize("n", [1000, (1 << 20) + 3])
 def test_in_place(n):
     _check(inputs.keyset("d", n, seed=3).keys, inplace=True)

@@ -112,6 +112,18 @@ def test_constant_and_clustered_segments():
     _check(keys, off.astype(np.uint32))
 
 
+@pytest.mark.parametrize("cfg", [None, 0, 3, 10])
+def test_segments_of_equal_key_runs(cfg):
+    """Segments made of runs of equal keys (lengths 1..199): rank slots switch between
+    all-lanes-equal digits and mixed ones, in every configuration's digit sweeps."""
+    rng = np.random.default_rng(99)
+    lens = rng.integers(1, 200, size=8000)
+    vals = rng.integers(0, 1 << 32, size=lens.size, dtype=np.uint64).astype(np.uint32)
+    keys = np.repeat(vals, lens)
+    seg = np.concatenate([[0], np.sort(rng.choice(np.arange(1, keys.size), size=63, replace=False)), [keys.size]])
+    _check(keys, seg.astype(np.uint32), cfg=cfg)
+
+
 def test_full_range_keys_and_unaligned_segments():
     rng = np.random.default_rng(9)
     keys = rng.integers(0, 1 << 32, size=300_001, dtype=np.uint64).astype(np.uint32)
