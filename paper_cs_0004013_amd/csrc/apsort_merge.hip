@@ -239,7 +239,8 @@ extern "C" {
 ap_status ap_merge_u32(const uint32_t* d_a, size_t na, const uint32_t* d_b, size_t nb, uint32_t* d_out,
                        void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (na + nb >= AP_MAX_KEYS) return fail(AP_ERR_INVALID, "na + nb must be < 2^30");
+  if (na >= AP_MAX_KEYS || nb >= AP_MAX_KEYS || na + nb >= AP_MAX_KEYS)
+    return fail(AP_ERR_INVALID, "na + nb must be < 2^30");
   if (na + nb == 0) return AP_OK;
   if ((na && !d_a) || (nb && !d_b) || !d_out) return fail(AP_ERR_INVALID, "NULL buffer with a nonzero count");
   if (((uintptr_t)d_a | (uintptr_t)d_b | (uintptr_t)d_out) & 3u)
@@ -254,8 +255,9 @@ ap_status ap_merge_u32(const uint32_t* d_a, size_t na, const uint32_t* d_b, size
 
 ap_status ap_merge_adjacent_u32(uint32_t* d_keys, size_t na, size_t nb, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (na >= AP_MAX_KEYS || nb >= AP_MAX_KEYS || na + nb >= AP_MAX_KEYS)
+    return fail(AP_ERR_INVALID, "na + nb must be < 2^30");
   const size_t n = na + nb;
-  if (n >= AP_MAX_KEYS) return fail(AP_ERR_INVALID, "na + nb must be < 2^30");
   if (n == 0 || na == 0 || nb == 0) return AP_OK;  // one run: already sorted
   if (!d_keys) return fail(AP_ERR_INVALID, "d_keys is NULL");
   if ((uintptr_t)d_keys & 3u) return fail(AP_ERR_INVALID, "d_keys must be 4-byte aligned");

@@ -71,3 +71,8 @@ def test_invalid_arguments_rejected_on_host():
     assert L.ap_sort_u32(4096, 4100, 10, 64, None, None) == 1          # partial overlap
     assert L.ap_digit_plan_u32(4096, 10, 3, 8192, None, None) == 1     # digit width
     assert L.ap_sort_u32_ws(4096, 8192, 1000, 4, None, 65536, 16, None) == 1  # workspace too small
+    assert L.ap_merge_u32(4096, (1 << 64) - 1, 8192, 1, 65536, None) == 1   # na + nb wraps around
+    assert L.ap_merge_u32(4096, 10, 8192, 10, 4100, None) == 1             # output overlaps a
+    assert L.ap_merge_u32(None, 10, 8192, 10, 65536, None) == 1            # NULL run
+    assert L.ap_merge_adjacent_u32(4096, 1 << 29, 1 << 29, None) == 1      # na + nb >= 2^30
+    assert L.ap_merge_adjacent_u32(4098, 10, 10, None) == 1                # misaligned
