@@ -73,6 +73,31 @@ def test_runs_of_equal_keys(seed):
     _check(keys)
 
 
+def test_maximum_size():
+    """n = 2^30 - 1 pairs (the largest n accepted), values 0..n-1, checked on the device by
+    properties that fix the stable sort uniquely: keys nondecreasing (unsigned), every output key
+    equal to the input key at its output value, and values increasing within runs of equal keys
+    (the values are then a permutation: a gather of n distinct positions in increasing order per
+    key)."""
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    n = (1 << 30) - 1
+    announce(f"pairs maximum size n={n}")
+    g = torch.Generator(device="cuda").manual_seed(3)
+    keys = torch.randint(-(1 << 31), 1 << 31, (n,), device="cuda", generator=g, dtype=torch.int32)
+    keys[: n // 2] &= 0xFFFF                      # half the keys from 2^16 values: long runs of ties
+    vals = torch.arange(n, device="cuda", dtype=torch.int32)
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(vals)
+    binding.ap_sort_pairs_u32(keys, vals, ko, vo, 64, None)
+    torch.cuda.synchronize()
+    flip = ko ^ torch.tensor(-(1 << 31), dtype=torch.int32, device="cuda")
+    assert bool((flip[1:] >= flip[:-1]).all())
+    del flip
+    assert bool((keys[vo.long()] == ko).all())
+    assert bool(((ko[1:] != ko[:-1]) | (vo[1:] > vo[:-1])).all())
+
+
 @pytest.mark.parametrize("n", [1000, (1 << 20) + 3])
 def test_in_place(n):
     _check(inputs.keyset("d", n, seed=3).keys, inplace=True)

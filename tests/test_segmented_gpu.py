@@ -124,6 +124,43 @@ def test_segments_of_equal_key_runs(cfg):
     _check(keys, seg.astype(np.uint32), cfg=cfg)
 
 
+def test_maximum_total_size():
+    """n_total = 2^30 - 1 keys in 4096 segments of random lengths, checked on the device: each
+    segment nondecreasing (unsigned), and the key sum and 2^16-bin histogram of the top 16 bits
+    of every segment unchanged."""
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    n = (1 << 30) - 1
+    rng = np.random.default_rng(4)
+    cuts = np.sort(rng.choice(np.arange(1, n), size=4095, replace=False))
+    off = np.concatenate([[0], cuts, [n]]).astype(np.uint32)
+    announce(f"segmented maximum total n={n}")
+    g = torch.Generator(device="cuda").manual_seed(4)
+    keys = torch.randint(-(1 << 31), 1 << 31, (n,), device="cuda", generator=g, dtype=torch.int32)
+    seg_id = torch.repeat_interleave(torch.arange(4096, device="cuda"),
+                                     torch.from_numpy(np.diff(off).astype(np.int64)).to("cuda"))
+    mask = (1 << 32) - 1
+
+    def sums(t):
+        return torch.zeros(4096, dtype=torch.int64, device="cuda").index_add_(0, seg_id, t.to(torch.int64) & mask)
+
+    def tops(t):
+        return torch.bincount(seg_id * 65536 + ((t >> 16) & 0xFFFF).to(torch.int64), minlength=4096 * 65536)
+
+    s_in, h_in = sums(keys), tops(keys)
+    t_off = torch.from_numpy(off.view(np.int32)).to("cuda")
+    st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    binding.ap_sort_u32_segmented(keys, t_off, st)
+    torch.cuda.synchronize()
+    assert int(st[0]) == 0
+    flip = keys ^ torch.tensor(-(1 << 31), dtype=torch.int32, device="cuda")
+    ok = (flip[1:] >= flip[:-1]) | (seg_id[1:] != seg_id[:-1])
+    del flip
+    assert bool(ok.all())
+    assert torch.equal(sums(keys), s_in)
+    assert torch.equal(tops(keys), h_in)
+
+
 def test_full_range_keys_and_unaligned_segments():
     rng = np.random.default_rng(9)
     keys = rng.integers(0, 1 << 32, size=300_001, dtype=np.uint64).astype(np.uint32)
