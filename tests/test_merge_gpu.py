@@ -75,3 +75,30 @@ def test_overlapping_output_rejected():
     x = torch.zeros(3000, dtype=torch.int32, device="cuda")
     with pytest.raises(binding.ApError):
         binding.ap_merge_u32(x[:1000], x[1000:2000], x[500:2500])
+
+
+def test_maximum_size():
+    """na + nb = 2^30 - 1 (the largest total accepted), runs of 31-bit keys (signed and unsigned
+    order agree), against torch's sort of the concatenation on the device; then the same runs as
+    one array through the adjacent-run merge."""
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    na, nb = 1 << 29, (1 << 29) - 1
+    announce(f"merge maximum size na={na} nb={nb}")
+    g = torch.Generator(device="cuda").manual_seed(6)
+    keys = torch.randint(0, 1 << 31, (na + nb,), device="cuda", generator=g, dtype=torch.int32)
+    keys[::7] &= 0xFF                                   # ties across the two runs
+    a = torch.sort(keys[:na])[0]
+    b = torch.sort(keys[na:])[0]
+    want = torch.sort(keys)[0]
+    del keys
+    out = torch.empty(na + nb, dtype=torch.int32, device="cuda")
+    binding.ap_merge_u32(a, b, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, want)
+    out[:na] = a
+    out[na:] = b
+    del a, b
+    binding.ap_merge_adjacent_u32(out, na)
+    torch.cuda.synchronize()
+    assert torch.equal(out, want)
