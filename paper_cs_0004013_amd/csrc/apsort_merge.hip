@@ -22,9 +22,9 @@
 
 namespace aps {
 
-constexpr int kMergeThreads = 256;
+constexpr int kMergeThreads = 512;
 constexpr int kMergeIpt = 16;
-constexpr uint32_t kMergeTile = kMergeThreads * kMergeIpt;  // 4096 outputs per workgroup
+constexpr uint32_t kMergeTile = kMergeThreads * kMergeIpt;  // 8192 outputs per workgroup
 
 // Number of keys of a among the first d outputs (ties: a first), known to lie in [lo, hi].
 // Evaluated by a group of G lanes of one wave (each group its own diagonal d): each round trip
