@@ -272,11 +272,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   __shared__ uint64_t s_bins[RANK == RANK_MATCH ? WAVES * R : 1];  // per-wave bucket lane masks
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // the tile claim's round trip overlaps the clearing of the counters; one barrier covers both
+  if (tid == 0) s_tile = add_agent(tile_ctr + d, 1u);
   for (int j = tid; j < WAVES * R; j += THREADS) s_cnt[j] = 0u;
   if constexpr (RANK == RANK_MATCH)
     for (int j = tid; j < WAVES * R; j += THREADS) s_bins[j] = 0ull;
-  __syncthreads();
-  if (tid == 0) s_tile = add_agent(tile_ctr + d, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
   const uint32_t tbase = tile * (uint32_t)T;
@@ -316,13 +316,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const uint32_t v = (k[j] >> shift) & (R - 1);
+      // Each step needs every lane of the wave to have finished the previous one: a wave's LDS
+      // instructions run for all its lanes before the next starts.  The wave barriers (no
+      // instruction, only a scheduling fence) state that order where lanes do not run together.
       __hip_atomic_fetch_or(&bins[v], mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __builtin_amdgcn_wave_barrier();
       const uint64_t m = __hip_atomic_load(&bins[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __builtin_amdgcn_wave_barrier();
       __hip_atomic_store(&bins[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
       const uint32_t peers = lanes_below(m);
       const uint32_t c = cnt[v];
+      __builtin_amdgcn_wave_barrier();
       r[j] = c + peers;
       if (peers == 0u) cnt[v] = c + (uint32_t)__popcll(m);
+      __builtin_amdgcn_wave_barrier();
     }
   }
 
