@@ -19,7 +19,7 @@ struct SegCfg {
   int bits, waves, ipt;
 };
 static const SegCfg kSegCfgs[] = {
-    {8, 8, 16},   // 0: 512 threads, 8192-key tiles (default for every group)
+    {8, 8, 16},   // 0: 512 threads, 8192-key tiles
     {8, 16, 8},   // 1: 1024 threads, 8192-key tiles
     {8, 4, 16},   // 2: 256 threads, 4096-key tiles
     {8, 4, 8},    // 3: 256 threads, 2048-key tiles
@@ -110,7 +110,7 @@ void seg_reset(hipStream_t s, SegCtl* ctl) { hipLaunchKernelGGL(k_seg_reset, dim
 // 4K-key tiles (512 threads), shorter ones with 2K-key tiles (256 threads).  The tuner rewrites
 // the table (ap_segmented_set_group, ap_load_tuning).
 static std::mutex g_grp_mu;
-static SegGroup g_groups[kSegGroups] = {{15, 31, 10}, {13, 14, 1}, {11, 12, 5}, {1, 10, 3}};
+static SegGroup g_groups[kSegGroups] = {{15, 31, 10}, {13, 14, 10}, {11, 12, 0}, {1, 10, 3}};
 static int g_groups_version = 0;  // bumped on every change (invalidates captured graphs)
 
 int seg_groups_version() {
