@@ -56,6 +56,10 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
   constexpr int HW = D * R;
   constexpr int CS = HW + 1;  // copy stride
   constexpr bool LANE_PRIV = (HW == 1024 && THREADS == 1024);
+  // a lane copy counts the keys of THREADS / 64 threads: at most 4 per vector plus one head and
+  // one tail key each
+  static_assert(!LANE_PRIV || (THREADS / 64) * (4 * kHistMaxVecPerThread + 2) < 65536u,
+                "16-bit lane counters would overflow");
   constexpr int HWORDS = LANE_PRIV ? (HW / 2) * 64 : LCOPIES * CS;
   __shared__ uint32_t h[HWORDS];
   __shared__ uint32_t s_const[kMaxDigits];
