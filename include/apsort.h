@@ -303,8 +303,10 @@ ap_status ap_server_get_stats(ap_server *s, ap_server_stats *out,
 ap_status ap_server_destroy(ap_server *s);
 
 /*
- * ap_release_cache -- free the scratch memory cached for ap_sort_u32 on the
- * current device (all streams).  Synchronises the device first.
+ * ap_release_cache -- free the scratch memory cached for ap_sort_u32,
+ * ap_sort_pairs_u32 and the merge entry points on the current device (all
+ * streams).  Synchronises the device first.  The segmented sort's per-stream
+ * scratch and graphs, and a server's slots, are not affected.
  */
 ap_status ap_release_cache(void);
 

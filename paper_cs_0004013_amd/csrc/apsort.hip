@@ -486,6 +486,7 @@ ap_status release_cache() {
     else keep.push_back(c);
   }
   g_cache.swap(keep);
+  release_merge_scratch(dev);
   return AP_OK;
 }
 

@@ -27,6 +27,8 @@ int device_cus();
 bool lane_order_ok();
 ap_status check_lane_order(hipStream_t s);
 ap_status fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s);
+// Frees the merge entry points' cached scratch of device `dev`; the device must be idle.
+void release_merge_scratch(int dev);
 // Kernel timing: prof_begin/prof_end bracket one launch when profiling is on for this thread.
 void prof_begin(int kind, hipStream_t s);
 void prof_end(hipStream_t s);

@@ -202,6 +202,17 @@ static ap_status merge_scratch(hipStream_t s, size_t words, uint32_t** out) {
   return AP_OK;
 }
 
+// Frees the merge scratch of device `dev` (every stream); the caller has synchronised the device.
+void release_merge_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_merge_mu);
+  std::vector<MergeEntry> keep;
+  for (auto& c : g_merge) {
+    if (c.dev == dev) (void)hipFree(c.buf);
+    else keep.push_back(c);
+  }
+  g_merge.swap(keep);
+}
+
 constexpr uint32_t kMergeRatio = 64;  // tiles per coarse partition window
 
 // scratch words: the tile splits, then the coarse splits

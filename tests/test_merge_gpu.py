@@ -102,3 +102,16 @@ def test_maximum_size():
     binding.ap_merge_adjacent_u32(out, na)
     torch.cuda.synchronize()
     assert torch.equal(out, want)
+
+
+def test_release_cache_between_merges():
+    """ap_release_cache frees the merge scratch too: merges before and after it (each one after a
+    release re-allocates) all match the oracle."""
+    from paper_cs_0004013_amd import binding
+    a, b = _runs(70_001, 65_536, 5)
+    assert np.array_equal(_merge(a, b), oracle.merge_u32(a, b))
+    binding.ap_release_cache()
+    a2, b2 = _runs(300_000, 123_457, 6)
+    assert np.array_equal(_merge(a2, b2), oracle.merge_u32(a2, b2))
+    binding.ap_release_cache()
+    assert np.array_equal(_merge(a, b), oracle.merge_u32(a, b))
