@@ -149,6 +149,23 @@ int main(void) {
   }
   if (memcmp(got, want, at * 4) != 0) { fprintf(stderr, "served keys differ\n"); return 1; }
 
+  /* merge of two sorted runs: into another buffer, and in place as adjacent runs of one array */
+  {
+    const size_t na = n / 3, nb = n - n / 3;
+    memcpy(want, h, n * 4);
+    qsort(want, na, 4, cmp_u32);
+    qsort(want + na, nb, 4, cmp_u32);
+    CHECK_HIP(hipMemcpy(d_out, want, n * 4, hipMemcpyHostToDevice));
+    CHECK_AP(ap_merge_u32(d_out, na, d_out + na, nb, d_in, NULL));
+    CHECK_AP(ap_merge_adjacent_u32(d_out, na, nb, NULL));
+    CHECK_HIP(hipDeviceSynchronize());
+    qsort(want, n, 4, cmp_u32);
+    CHECK_HIP(hipMemcpy(got, d_in, n * 4, hipMemcpyDeviceToHost));
+    if (memcmp(got, want, n * 4) != 0) { fprintf(stderr, "merged runs differ\n"); return 1; }
+    CHECK_HIP(hipMemcpy(got, d_out, n * 4, hipMemcpyDeviceToHost));
+    if (memcmp(got, want, n * 4) != 0) { fprintf(stderr, "adjacent-run merge differs\n"); return 1; }
+  }
+
   hipFree(d_in); hipFree(d_out); hipFree(d_spl); hipFree(d_off); hipFree(d_st); hipFree(d_ws);
   free(h); free(want); free(got);
   printf("consumer ok (%s)\n", ap_version());
