@@ -212,8 +212,9 @@ size_t ap_segmented_workspace_bytes(size_t n_total, int nseg);
 
 /*
  * Segmented-sort tuning.  Segments (and batched server requests) fall in
- * length groups: group g covers the lengths whose floor(log2(length)) lies in
- * [cls_lo, cls_hi] and runs kernel configuration cfg (digit width, waves per
+ * length groups: group g covers the lengths whose length class, ceil(log2(length))
+ * (lengths 0..2 count as class 1), lies in [cls_lo, cls_hi] and runs kernel
+ * configuration cfg (digit width, waves per
  * workgroup, keys per lane; ap_segmented_num_configs() configurations are
  * compiled in, see ap_segmented_config_info).  The groups must not overlap;
  * a group with cls_lo > cls_hi is unused.  Settings are process-wide.
@@ -224,6 +225,7 @@ size_t ap_segmented_workspace_bytes(size_t n_total, int nseg);
  *                         as written by the package's autotuner
  */
 int ap_segmented_num_configs(void);
+int ap_segmented_num_groups(void);  /* number of length groups g */
 ap_status ap_segmented_config_info(int cfg, int *digit_bits, int *waves,
                                    int *keys_per_lane);
 ap_status ap_segmented_set_config(int cfg);

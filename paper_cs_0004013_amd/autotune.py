@@ -1,8 +1,8 @@
 """Autotuner of the segmented sort: picks the kernel configuration (digit width, waves per
 workgroup, keys per lane) of each length group by measurement.
 
-The length groups are fixed ranges of floor(log2(segment length)) classes: >= 32K keys, 8K..32K-1,
-2K..8K-1 and 2..2047.  The tuning batch has the workload's shape: 4096 segments with lengths
+The length groups are fixed ranges of length classes ceil(log2(segment length)), one per tile
+size: more than 16K keys, (8K, 16K], (4K, 8K], (2K, 4K] and up to 2K.  The tuning batch has the workload's shape: 4096 segments with lengths
 log-uniform in [64, 2^18] and distributions (a)-(e) by segment seed; three such batches are
 drawn with seeds of their own (not the benchmark's), because which configuration wins depends on
 the particular lengths (the longest segments set the critical path).  The groups are tuned by
@@ -26,8 +26,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tune_gfx950.txt")
-GROUPS = [(15, 31), (13, 14), (11, 12), (1, 10)]   # >= 32K, 8K..32K-1, 2K..8K-1, 2..2047 keys
-START = [10, 10, 0, 3]                              # configurations the descent starts from (the installed table)
+GROUPS = [(15, 31), (14, 14), (13, 13), (12, 12), (1, 11)]   # > 16K, (8K, 16K], (4K, 8K], (2K, 4K], <= 2K keys
+START = [10, 10, 1, 5, 3]                                     # configurations the descent starts from (the built-in table)
 TUNE_SEEDS = (7919, 104729, 1299709)
 
 
@@ -103,7 +103,7 @@ def tune(reps: int = 5, rounds: int = 2, out: str | None = DEFAULT_TABLE, verbos
     chosen = [(lo, hi, c) for (lo, hi), c in zip(GROUPS, choice)]
     if out:
         with open(out, "w") as f:
-            f.write("# segmented-sort length groups: group cls_lo cls_hi cfg  (floor(log2 length) classes)\n")
+            f.write("# segmented-sort length groups: group cls_lo cls_hi cfg  (ceil(log2 length) classes)\n")
             f.write("# written by paper_cs_0004013_amd.autotune (coordinate descent on three 4096-segment batches)\n")
             for g, (lo, hi, cfg) in enumerate(chosen):
                 f.write(f"{g} {lo} {hi} {cfg}\n")

@@ -49,6 +49,7 @@ SIGNATURES = [
     ("ap_sort_u32_segmented", _I, [_VP, _SZ, _VP, _I, _VP, _VP]),
     ("ap_segmented_workspace_bytes", _SZ, [_SZ, _I]),
     ("ap_segmented_num_configs", _I, []),
+    ("ap_segmented_num_groups", _I, []),
     ("ap_segmented_config_info", _I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     ("ap_segmented_set_config", _I, [_I]),
     ("ap_segmented_set_group", _I, [_I, _I, _I, _I]),
@@ -287,7 +288,8 @@ def ap_segmented_set_config(cfg: int) -> None:
     check(lib().ap_segmented_set_config(cfg), "ap_segmented_set_config")
 
 
-SEG_GROUPS = 4
+def ap_segmented_num_groups() -> int:
+    return int(lib().ap_segmented_num_groups())
 
 
 def ap_segmented_config_info(cfg: int) -> tuple[int, int, int]:
@@ -301,7 +303,7 @@ def ap_segmented_config_info(cfg: int) -> tuple[int, int, int]:
 def segmented_groups() -> list[tuple[int, int, int]]:
     """Current (cls_lo, cls_hi, cfg) of every length group."""
     out = []
-    for g in range(SEG_GROUPS):
+    for g in range(ap_segmented_num_groups()):
         a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(lib().ap_segmented_get_group(g, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
               "ap_segmented_get_group")
@@ -310,7 +312,13 @@ def segmented_groups() -> list[tuple[int, int, int]]:
 
 
 def set_segmented_groups(groups) -> None:
-    for g, (lo, hi, cfg) in enumerate(groups):
+    """Install (cls_lo, cls_hi, cfg) as groups 0.. in order; the groups not listed become unused."""
+    groups = list(groups)
+    ng = ap_segmented_num_groups()
+    if len(groups) > ng:
+        raise ValueError(f"at most {ng} length groups")
+    for g in range(ng):
+        lo, hi, cfg = groups[g] if g < len(groups) else (1, 0, 0)
         check(lib().ap_segmented_set_group(g, lo, hi, cfg), "ap_segmented_set_group")
 
 

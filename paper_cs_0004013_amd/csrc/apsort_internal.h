@@ -38,7 +38,7 @@ bool prof_active();
 struct SegDesc;
 struct SegCtl;
 struct SegGroup {
-  int cls_lo, cls_hi, cfg;  // floor(log2(length)) range and kernel configuration
+  int cls_lo, cls_hi, cfg;  // ceil(log2(length)) class range and kernel configuration
 };
 void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
                     int cls_hi, int grp, SegCtl* ctl);

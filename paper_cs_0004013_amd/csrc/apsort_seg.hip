@@ -104,13 +104,14 @@ int seg_tile_keys(int cfg) { return kSegCfgs[cfg].waves * 64 * kSegCfgs[cfg].ipt
 
 void seg_reset(hipStream_t s, SegCtl* ctl) { hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, s, ctl); }
 
-// Length groups: group g sorts the segments whose floor(log2(length)) lies in [cls_lo, cls_hi] with
-// kernel configuration cfg.  Defaults (the table measured on gfx950 by the tuner): >= 32K keys
-// with 16K-key tiles (1024 threads), 8K..32K-1 with 8K-key tiles (1024 threads), 2K..8K-1 with
-// 4K-key tiles (512 threads), shorter ones with 2K-key tiles (256 threads).  The tuner rewrites
-// the table (ap_segmented_set_group, ap_load_tuning).
+// Length groups: group g sorts the segments whose length class ceil(log2(length)) lies in
+// [cls_lo, cls_hi] with kernel configuration cfg.  The defaults give each tile size its own
+// class: up to 2K keys with 2K-key tiles, (2K, 4K] with 4K-key tiles, (4K, 8K] with 8K-key tiles,
+// (8K, 16K] with 16K-key tiles, longer segments with 16K-key tiles and digit sweeps.  The tuner
+// rewrites the table (ap_segmented_set_group, ap_load_tuning).
 static std::mutex g_grp_mu;
-static SegGroup g_groups[kSegGroups] = {{15, 31, 10}, {13, 14, 10}, {11, 12, 0}, {1, 10, 3}};
+// length classes ceil(log2(len)): one group per tile size (16K, 8K, 4K, 2K keys) and one for longer segments
+static SegGroup g_groups[kSegGroups] = {{15, 31, 10}, {14, 14, 10}, {13, 13, 1}, {12, 12, 5}, {1, 11, 3}, {1, 0, 0}};
 static int g_groups_version = 0;  // bumped on every change (invalidates captured graphs)
 
 int seg_groups_version() {
@@ -390,6 +391,8 @@ ap_status ap_load_tuning(const char* path) {
 }
 
 int ap_segmented_num_configs(void) { return kNumSegCfgs; }
+
+int ap_segmented_num_groups(void) { return kSegGroups; }
 
 ap_status ap_segmented_config_info(int cfg, int* digit_bits, int* waves, int* keys_per_lane) {
   if (cfg < 0 || cfg >= kNumSegCfgs || !digit_bits || !waves || !keys_per_lane)

@@ -19,7 +19,10 @@
 
 namespace aps {
 
-__device__ __forceinline__ int seg_class(uint32_t len) { return 31 - __clz(len); }
+// Length class ceil(log2(len)) for len >= 2: class c holds lengths in (2^(c-1), 2^c], so a
+// configuration whose tile holds 2^c keys sorts every segment of class c in one tile, and
+// power-of-two lengths fill their tile exactly.
+__device__ __forceinline__ int seg_class(uint32_t len) { return 32 - __clz(len - 1u); }
 
 // Pass 1: validate offsets (off[s] <= off[s+1] <= n_total for every s), count segments per length
 // class; the last workgroup turns the counts into a longest-first order of classes, or into an

@@ -5,8 +5,8 @@
 
 namespace aps {
 
-constexpr int kSegBuckets = 32;  // work-list classes: floor(log2(length))
-constexpr int kSegGroups = 4;    // length groups, each sorted by its own kernel configuration
+constexpr int kSegBuckets = 32;  // work-list classes: ceil(log2(length))
+constexpr int kSegGroups = 6;    // length groups, each sorted by its own kernel configuration
 
 // Control block of the segmented sort (device memory, zero between calls).
 struct SegCtl {

@@ -113,7 +113,7 @@ class HipExecutor : public srv::Executor {
       uint32_t lo = cnt, hi = 0;
       for (uint32_t i = 0; i < cnt; ++i) {
         const uint32_t n = sl.h_desc[i].n;
-        const int c = n < 2 ? 1 : 31 - __builtin_clz(n);
+        const int c = n < 2 ? 1 : 32 - __builtin_clz(n - 1u);  // ceil(log2(n)), as on the device
         if (c >= grp[g].cls_lo && c <= grp[g].cls_hi) {
           lo = std::min(lo, i);
           hi = i + 1;
