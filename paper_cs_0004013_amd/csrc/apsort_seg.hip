@@ -106,12 +106,13 @@ void seg_reset(hipStream_t s, SegCtl* ctl) { hipLaunchKernelGGL(k_seg_reset, dim
 
 // Length groups: group g sorts the segments whose length class ceil(log2(length)) lies in
 // [cls_lo, cls_hi] with kernel configuration cfg.  The defaults give each tile size its own
-// class: up to 2K keys with 2K-key tiles, (2K, 4K] with 4K-key tiles, (4K, 8K] with 8K-key tiles,
-// (8K, 16K] with 16K-key tiles, longer segments with 16K-key tiles and digit sweeps.  The tuner
+// classes: up to 2K keys with 2K-key tiles, (2K, 4K] with 4K-key tiles, (4K, 8K] with 8K-key
+// tiles, and above 8K with 16K-key tiles (longer segments by digit sweeps).  Every group is one
+// more concurrent persistent kernel, so classes sharing a configuration share a group.  The tuner
 // rewrites the table (ap_segmented_set_group, ap_load_tuning).
 static std::mutex g_grp_mu;
-// length classes ceil(log2(len)): one group per tile size (16K, 8K, 4K, 2K keys) and one for longer segments
-static SegGroup g_groups[kSegGroups] = {{15, 31, 10}, {14, 14, 10}, {13, 13, 1}, {12, 12, 5}, {1, 11, 3}, {1, 0, 0}};
+// length classes ceil(log2(len)): one group per tile size (16K keys, also taking longer segments; 8K; 4K; 2K)
+static SegGroup g_groups[kSegGroups] = {{14, 31, 10}, {13, 13, 1}, {12, 12, 5}, {1, 11, 3}, {1, 0, 0}, {1, 0, 0}};
 static int g_groups_version = 0;  // bumped on every change (invalidates captured graphs)
 
 int seg_groups_version() {
