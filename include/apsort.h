@@ -216,8 +216,13 @@ size_t ap_segmented_workspace_bytes(size_t n_total, int nseg);
  * (lengths 0..2 count as class 1), lies in [cls_lo, cls_hi] and runs kernel
  * configuration cfg (digit width, waves per
  * workgroup, keys per lane; ap_segmented_num_configs() configurations are
- * compiled in, see ap_segmented_config_info).  The groups must not overlap;
- * a group with cls_lo > cls_hi is unused.  Settings are process-wide.
+ * compiled in, see ap_segmented_config_info).  A group with cls_lo > cls_hi
+ * is unused; the used groups must cover every class 1..31 exactly once.
+ * ap_load_tuning rejects a table that does not (AP_ERR_INVALID, nothing
+ * installed); a table built group by group with ap_segmented_set_group is
+ * checked when a segmented sort or a server batch is launched, which then
+ * fails with AP_ERR_INVALID (nothing enqueued; for the server, every request
+ * of the batch completes with AP_ERR_DEVICE).  Settings are process-wide.
  *   ap_segmented_set_config(cfg)  every group uses cfg
  *   ap_segmented_set_group / ap_segmented_get_group  one group
  *   ap_load_tuning(path)  replace the table from a text file with lines
@@ -327,18 +332,21 @@ ap_status ap_profile_enable(int on);
 ap_status ap_profile_read(double *ms, uint64_t *launches, int nkinds);
 
 /*
- * Rank primitive of the digit pass.  The default rank gives each key the
- * value returned by an LDS atomic add on a per-wave bucket counter, which is
- * stable because the LDS services the conflicting lanes of one instruction in
- * lane order; a device self-check (run once per device by the first
- * ap_sort_u32, ap_workspace_init or ap_server_create) confirms that property
- * before it is relied on.  The alternative rank builds per-bucket lane masks
- * in LDS and needs no ordering property.
+ * Rank primitive of every digit pass (single array, pairs, segmented and
+ * served sorts).  The default rank gives each key the value returned by an
+ * LDS atomic add on a per-wave bucket counter, which is stable because the LDS
+ * services the conflicting lanes of one instruction in lane order; a device
+ * self-check (run once per device by the first ap_sort_u32,
+ * ap_sort_u32_segmented, ap_workspace_init or ap_server_create) confirms that
+ * property before it is relied on.  Until then, or when it fails, the
+ * alternative ranks run, which need no ordering property: per-bucket lane
+ * masks in LDS (device-wide passes) and one ballot per digit bit (segmented
+ * and served sorts).
  *
  * ap_rank_check_state: -1 = device not checked yet, 0 = check failed (the
- * mask rank is used), 1 = check passed (the atomic rank is used).
- * ap_set_rank_mode: 0 = automatic (default), 1 = always the mask rank
- * (process-wide; for testing both paths).
+ * order-agnostic ranks are used), 1 = check passed (the atomic rank is used).
+ * ap_set_rank_mode: 0 = automatic (default), 1 = always the order-agnostic
+ * ranks (process-wide; for testing both paths).
  */
 int ap_rank_check_state(void);
 ap_status ap_set_rank_mode(int mode);

@@ -91,25 +91,12 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        _bind_extra(L)
         if os.path.exists(TUNE_TABLE):
             st = L.ap_load_tuning(TUNE_TABLE.encode())
             if st != AP_OK:
                 raise ApError(st, "ap_load_tuning", L.ap_last_error().decode(errors="replace"))
         _lib = L
     return _lib
-
-
-def _bind_extra(L):
-    """Entry points of the batched and served forms (declared when present in the library)."""
-    for name, res, args in EXTRA_SIGNATURES:
-        f = getattr(L, name, None)
-        if f is not None:
-            f.restype = res
-            f.argtypes = args
-
-
-EXTRA_SIGNATURES: list = []
 
 
 def last_error() -> str:

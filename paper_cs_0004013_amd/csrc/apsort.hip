@@ -447,10 +447,12 @@ ap_status cached_workspace(size_t need, hipStream_t s, void** out) {
       }
       e = hipStreamSynchronize(s);  // the old block may still be in use on this stream
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      // grow geometrically (at least by a quarter) so that slowly growing calls do not
+      // reallocate every time
+      const size_t bytes = std::max(need, c.bytes + c.bytes / 4);
       (void)hipFree(c.ptr);
       c.ptr = nullptr;
       c.bytes = 0;
-      const size_t bytes = std::max(need, c.bytes + c.bytes / 4);
       e = hipMalloc(&c.ptr, bytes);
       if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
       c.bytes = bytes;

@@ -56,6 +56,23 @@ __device__ __forceinline__ uint64_t match_any(uint32_t v) {
 }
 
 // Stable rank of this lane's digit v among the wave's keys ranked so far, against the wave's own
+// LDS counters cnt (one word per digit), with no assumption on the order in which the LDS serves
+// conflicting lanes: the lanes sharing v are found with match_any, a lane's rank is the counter
+// plus the number of those lanes below it, and the lowest of them advances the counter.  Every
+// lane of the wave must be active.  A wave's LDS instructions run in program order, so every
+// lane's read of the counter completes before the leaders write it.
+template <int BITS>
+__device__ __forceinline__ uint32_t rank_ballot(uint32_t* cnt, uint32_t v) {
+  const uint64_t m = match_any<BITS>(v);
+  const uint32_t peers = lanes_below(m);
+  const uint32_t c = cnt[v];
+  __builtin_amdgcn_wave_barrier();
+  if (peers == 0u) cnt[v] = c + (uint32_t)__popcll(m);
+  __builtin_amdgcn_wave_barrier();
+  return c + peers;
+}
+
+// Stable rank of this lane's digit v among the wave's keys ranked so far, against the wave's own
 // LDS counters cnt (one word per digit).  LDS executes one wave's instructions in order and
 // services the conflicting lanes of one instruction in lane order, so the value an atomic
 // increment returns is the number of this wave's earlier keys (earlier instructions, then lower

@@ -45,11 +45,14 @@ void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uin
 int seg_workgroups(int cfg, uint32_t nwork);
 int seg_tile_keys(int cfg);
 void seg_groups(SegGroup* out);  // kSegGroups entries
+ap_status seg_groups_check(const SegGroup* grp);  // the used groups partition classes 1..31
 void seg_reset(hipStream_t s, SegCtl* ctl);
 // d_vout != nullptr: (key, value) pairs, the values read from d_vin and written to d_vout
 // (workspace from layout_for(n, true)).
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
                        const Layout& L, hipStream_t s, const uint32_t* d_vin = nullptr, uint32_t* d_vout = nullptr);
+
+ap_status check_sort_args(const uint32_t* d_in, const uint32_t* d_out, size_t n, int P);
 
 ap_status enqueue_digit_plan(const uint32_t* d_in, size_t n, int bits, uint32_t* d_hist, uint32_t* d_plan,
                              hipStream_t s);

@@ -41,11 +41,18 @@ constexpr int seg_lcopies() {
   return c < 1 ? 1 : (c > 15 ? 15 : c);
 }
 
+// The rank with lane-ordered LDS atomics only on a device that passed the lane-order check
+// (lane_order_ok(), also false while the mask rank is forced by ap_set_rank_mode(1)); the ballot
+// rank otherwise.
 template <int BITS, int WAVES, int IPT>
 static void launch_seg_sort(dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
                             int cls_hi, int grp, SegCtl* ctl) {
-  hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, seg_lcopies<BITS>()>), grid, dim3(WAVES * 64), 0, s, order, lo,
-                     hi, cls_lo, cls_hi, grp, ctl);
+  if (lane_order_ok())
+    hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, seg_lcopies<BITS>(), SEG_RANK_ATOMIC>), grid, dim3(WAVES * 64),
+                       0, s, order, lo, hi, cls_lo, cls_hi, grp, ctl);
+  else
+    hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, seg_lcopies<BITS>(), SEG_RANK_BALLOT>), grid, dim3(WAVES * 64),
+                       0, s, order, lo, hi, cls_lo, cls_hi, grp, ctl);
 }
 
 // One persistent kernel of configuration cfg over work items [lo, hi) (or, with hi == ~0u, over
@@ -125,6 +132,27 @@ void seg_groups(SegGroup* out) {
   for (int g = 0; g < kSegGroups; ++g) out[g] = g_groups[g];
 }
 
+// The used groups (cls_lo <= cls_hi) must cover every length class 1..31 exactly once.  Two
+// groups sharing a class would both sort its segments, concurrently, in place through the same
+// scratch; a class no group covers would never be sorted.  AP_ERR_INVALID otherwise.
+ap_status seg_groups_check(const SegGroup* grp) {
+  int owner[32];
+  for (int c = 0; c < 32; ++c) owner[c] = -1;
+  for (int g = 0; g < kSegGroups; ++g) {
+    if (grp[g].cls_lo > grp[g].cls_hi) continue;
+    if (grp[g].cls_lo < 1 || grp[g].cls_hi > 31)
+      return fail(AP_ERR_INVALID, "length group %d: classes [%d, %d] outside [1, 31]", g, grp[g].cls_lo, grp[g].cls_hi);
+    for (int c = grp[g].cls_lo; c <= grp[g].cls_hi; ++c) {
+      if (owner[c] >= 0)
+        return fail(AP_ERR_INVALID, "length groups %d and %d both cover length class %d", owner[c], g, c);
+      owner[c] = g;
+    }
+  }
+  for (int c = 1; c <= 31; ++c)
+    if (owner[c] < 0) return fail(AP_ERR_INVALID, "no length group covers length class %d", c);
+  return AP_OK;
+}
+
 
 // Workspace: [SegCtl | pad to 256][order: nseg descriptors | pad][tmp n_total u32]
 struct SegLayout {
@@ -188,10 +216,12 @@ static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out) {
       if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
       if (c.exec) (void)hipGraphExecDestroy(c.exec);
       c.exec = nullptr;
+      // grow geometrically (at least by a quarter) so that slowly growing calls do not
+      // reallocate every time
+      const size_t bytes = std::max(need, c.bytes + c.bytes / 4);
       (void)hipFree(c.ws);
       c.ws = nullptr;
       c.bytes = 0;
-      const size_t bytes = std::max(need, c.bytes + c.bytes / 4);
       e = hipMalloc(&c.ws, bytes);
       if (e != hipSuccess) return hip_fail(e, "hipMalloc(segmented workspace)");
       c.bytes = bytes;
@@ -279,12 +309,19 @@ ap_status ap_sort_u32_segmented(uint32_t* d_keys, size_t n_total, const uint32_t
   if (!d_offsets) return fail(AP_ERR_INVALID, "d_offsets is NULL");
   if (n_total && !d_keys) return fail(AP_ERR_INVALID, "d_keys is NULL with n_total > 0");
   if (((uintptr_t)d_keys | (uintptr_t)d_offsets) & 3u) return fail(AP_ERR_INVALID, "pointers must be 4-byte aligned");
+  {
+    SegGroup grp[kSegGroups];
+    seg_groups(grp);
+    ap_status gst = seg_groups_check(grp);
+    if (gst != AP_OK) return gst;
+  }
   const SegLayout L = seg_layout(n_total, nseg);
   std::lock_guard<std::mutex> lk(g_seg_mu);
   SegEntry* ent = nullptr;
   ap_status st = seg_entry(s, L.total, &ent);
   if (st != AP_OK) return st;
-  const int cfg = seg_groups_version();
+  // graph key: the group table and the rank primitive (both baked into the captured kernels)
+  const int cfg = seg_groups_version() * 2 + (lane_order_ok() ? 1 : 0);
 
   // Replay a captured graph when the call repeats the previous one on this stream; capture
   // otherwise (only on a non-default stream that is not itself being captured).
@@ -385,6 +422,8 @@ ap_status ap_load_tuning(const char* path) {
   }
   std::fclose(f);
   if (!seen) return fail(AP_ERR_INVALID, "no tuning entries in %s", path);
+  ap_status st = seg_groups_check(next);
+  if (st != AP_OK) return st;
   std::lock_guard<std::mutex> lk(g_grp_mu);
   for (int g = 0; g < kSegGroups; ++g) g_groups[g] = next[g];
   ++g_groups_version;

@@ -135,10 +135,15 @@ __device__ __forceinline__ void seg_splitters(const SegDesc& dsc, uint32_t len) 
   }
 }
 
-// Tile rank of the keys k[] (wave-striped order) by the digit at `shift`: per-wave LDS counters
-// with lane-ordered atomics, then one scan gives cnt[w][v] = tile-local start of wave w's run of
-// bucket v, lbase (bucket starts) and tot (bucket totals).
-template <int BITS, int WAVES, int IPT, int LCOPIES>
+// Tile rank of the keys k[] (wave-striped order) by the digit at `shift`: per-wave LDS counters,
+// then one scan gives cnt[w][v] = tile-local start of wave w's run of bucket v, lbase (bucket
+// starts) and tot (bucket totals).  SEG_RANK_ATOMIC ranks with lane-ordered LDS atomics
+// (rank_slot), which the host selects only on a device that passed the lane-order check;
+// SEG_RANK_BALLOT ranks with one ballot per digit bit (rank_ballot) and needs no ordering
+// property of the LDS.
+enum SegRank : int { SEG_RANK_ATOMIC = 0, SEG_RANK_BALLOT = 1 };
+
+template <int BITS, int WAVES, int IPT, int LCOPIES, int RANK>
 __device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>& sm, const uint32_t (&k)[IPT],
                                               uint32_t (&r)[IPT], int shift) {
   constexpr int R = 1 << BITS, THREADS = WAVES * 64;
@@ -146,8 +151,13 @@ __device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>
   for (int j = tid; j < WAVES * R; j += THREADS) sm.u.p.cnt[j] = 0u;
   __syncthreads();
   uint32_t* cnt = sm.u.p.cnt + wid * R;
+  if constexpr (RANK == SEG_RANK_ATOMIC) {
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) r[j] = rank_slot(cnt, (k[j] >> shift) & (R - 1));
+    for (int j = 0; j < IPT; ++j) r[j] = rank_slot(cnt, (k[j] >> shift) & (R - 1));
+  } else {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) r[j] = rank_ballot<BITS>(cnt, (k[j] >> shift) & (R - 1));
+  }
   tile_bucket_offsets<R, WAVES>(sm.u.p.cnt, sm.lbase, sm.scan);
   for (int b = tid; b < R; b += THREADS) sm.tot[b] = sm.lbase[b + 1] - sm.lbase[b];
   __syncthreads();
@@ -157,7 +167,7 @@ __device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>
 // item_hi == ~0u the range is that of the length classes [cls_lo, cls_hi] in the device-built
 // work order (classes are stored longest first); otherwise it is [item_lo, item_hi).  Work items
 // are taken from ctl->head[grp].
-template <int BITS, int WAVES, int IPT, int LCOPIES>
+template <int BITS, int WAVES, int IPT, int LCOPIES, int RANK>
 __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restrict__ order, uint32_t item_lo,
                                                         uint32_t item_hi, int cls_lo, int cls_hi, int grp,
                                                         SegCtl* __restrict__ ctl) {
@@ -194,7 +204,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
 #pragma unroll 1
       for (int d = 0; d < D; ++d) {
         const int shift = d * BITS;
-        seg_rank_tile<BITS, WAVES, IPT, LCOPIES>(sm, k, r, shift);
+        seg_rank_tile<BITS, WAVES, IPT, LCOPIES, RANK>(sm, k, r, shift);
         // constant digit over the segment's keys (sentinels sit in the largest bucket)
         if (tid == 0) sm.flag[0] = 0u;
         __syncthreads();
@@ -292,7 +302,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
       for (uint32_t t = 0; t < ntile; ++t) {
         const uint32_t tb = t * (uint32_t)T;
         uint32_t r[IPT];
-        seg_rank_tile<BITS, WAVES, IPT, LCOPIES>(sm, k, r, shift);
+        seg_rank_tile<BITS, WAVES, IPT, LCOPIES, RANK>(sm, k, r, shift);
         uint32_t* cnt = sm.u.p.cnt + wid * R;
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {

@@ -108,6 +108,8 @@ class HipExecutor : public srv::Executor {
     // (lengths 0 and 1 count as class 1).
     SegGroup grp[kSegGroups];
     seg_groups(grp);
+    ap_status gst = seg_groups_check(grp);
+    if (gst != AP_OK) return gst;
     for (int g = 0; g < kSegGroups; ++g) {
       if (grp[g].cls_lo > grp[g].cls_hi) continue;
       uint32_t lo = cnt, hi = 0;

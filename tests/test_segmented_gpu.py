@@ -125,9 +125,8 @@ def test_segments_of_equal_key_runs(cfg):
 
 
 def test_maximum_total_size():
-    """n_total = 2^30 - 1 keys in 4096 segments of random lengths, checked on the device: each
-    segment nondecreasing (unsigned), and the key sum and 2^16-bin histogram of the top 16 bits
-    of every segment unchanged."""
+    """n_total = 2^30 - 1 full-range keys in 4096 segments of random lengths, compared element by
+    element with the oracle's per-segment sort on the host."""
     torch = torch_cuda()
     from paper_cs_0004013_amd import binding
     n = (1 << 30) - 1
@@ -137,28 +136,83 @@ def test_maximum_total_size():
     announce(f"segmented maximum total n={n}")
     g = torch.Generator(device="cuda").manual_seed(4)
     keys = torch.randint(-(1 << 31), 1 << 31, (n,), device="cuda", generator=g, dtype=torch.int32)
-    seg_id = torch.repeat_interleave(torch.arange(4096, device="cuda"),
-                                     torch.from_numpy(np.diff(off).astype(np.int64)).to("cuda"))
-    mask = (1 << 32) - 1
-
-    def sums(t):
-        return torch.zeros(4096, dtype=torch.int64, device="cuda").index_add_(0, seg_id, t.to(torch.int64) & mask)
-
-    def tops(t):
-        return torch.bincount(seg_id * 65536 + ((t >> 16) & 0xFFFF).to(torch.int64), minlength=4096 * 65536)
-
-    s_in, h_in = sums(keys), tops(keys)
+    h_keys = to_host(keys)
     t_off = torch.from_numpy(off.view(np.int32)).to("cuda")
     st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
     binding.ap_sort_u32_segmented(keys, t_off, st)
     torch.cuda.synchronize()
     assert int(st[0]) == 0
-    flip = keys ^ torch.tensor(-(1 << 31), dtype=torch.int32, device="cuda")
-    ok = (flip[1:] >= flip[:-1]) | (seg_id[1:] != seg_id[:-1])
-    del flip
-    assert bool(ok.all())
-    assert torch.equal(sums(keys), s_in)
-    assert torch.equal(tops(keys), h_in)
+    got = to_host(keys)
+    del keys
+    want = oracle.sort_segmented(h_keys, off.astype(np.uint64))
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, f"{bad.size} mismatches, first at {bad[:5]}"
+
+
+def test_benchmark_batch_4096():
+    """The benchmark's batch itself: 4096 segments, lengths log-uniform in [64, 2^18] (seed 0),
+    segment s drawn with seed s, against the oracle element by element."""
+    L = inputs.segment_lengths(4096, seed=0)
+    keys, off = _batch(L)
+    _check(keys, off)
+
+
+@pytest.fixture
+def order_agnostic_rank():
+    """Rank mode 1: the segmented kernels rank with ballots instead of lane-ordered LDS atomics."""
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_rank_mode(1)
+    try:
+        yield
+    finally:
+        binding.ap_set_rank_mode(0)
+
+
+def test_ballot_rank_log_uniform_512(order_agnostic_rank):
+    L = inputs.segment_lengths(512, seed=0)
+    keys, off = _batch(L)
+    _check(keys, off)
+
+
+@pytest.mark.parametrize("cfg", range(N_CONFIGS))
+def test_ballot_rank_every_config(cfg, order_agnostic_rank):
+    L = inputs.segment_lengths(64, seed=cfg + 40, lo=2, hi=1 << 16)
+    L[::9] = 1
+    keys, off = _batch(L)
+    _check(keys, off, cfg=cfg)
+
+
+@pytest.mark.parametrize("cfg", [None, 3, 10])
+def test_ballot_rank_equal_key_runs(cfg, order_agnostic_rank):
+    rng = np.random.default_rng(98)
+    lens = rng.integers(1, 200, size=6000)
+    vals = rng.integers(0, 1 << 32, size=lens.size, dtype=np.uint64).astype(np.uint32)
+    keys = np.repeat(vals, lens)
+    seg = np.concatenate([[0], np.sort(rng.choice(np.arange(1, keys.size), size=47, replace=False)), [keys.size]])
+    _check(keys, seg.astype(np.uint32), cfg=cfg)
+
+
+def test_ballot_rank_graph_recaptured():
+    """Switching the rank mode between calls with identical arguments re-captures the graph: the
+    replayed sequence never keeps the other rank's kernels."""
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    L = inputs.segment_lengths(48, seed=12)
+    keys, off = _batch(L)
+    want = oracle.sort_segmented(keys, off.astype(np.uint64))
+    s = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(s):
+            t_off = torch.from_numpy(off.view(np.int32)).to("cuda")
+            t_keys, _ = to_dev(keys)
+            for mode in (0, 1, 1, 0):
+                binding.ap_set_rank_mode(mode)
+                t_keys.copy_(torch.from_numpy(keys.view(np.int32)).to("cuda"))
+                binding.ap_sort_u32_segmented(t_keys, t_off)
+                s.synchronize()
+                assert np.array_equal(to_host(t_keys), want), mode
+    finally:
+        binding.ap_set_rank_mode(0)
 
 
 def test_full_range_keys_and_unaligned_segments():

@@ -70,12 +70,22 @@ def test_mixed_sizes_match_oracle():
     assert stats["alone"] >= 1                   # long ones ran device-wide
 
 
-def test_alone_vs_mix_identical():
-    """Each request gives byte-identical output run alone and inside a Poisson mix."""
+@pytest.mark.parametrize("rank_mode", [0, 1])
+def test_alone_vs_mix_identical(rank_mode):
+    """Each request gives byte-identical output run alone and inside a Poisson mix, with the
+    default rank and with the order-agnostic one (rank mode 1)."""
     from paper_cs_0004013_amd import binding
     pool = Pool(1 << 20)
     reqs = _requests(pool, 48, 1 << 10, 1 << 19, seed=2)
-    announce("server alone vs mix")
+    announce(f"server alone vs mix, rank mode {rank_mode}")
+    binding.ap_set_rank_mode(rank_mode)
+    try:
+        _alone_vs_mix(binding, pool, reqs)
+    finally:
+        binding.ap_set_rank_mode(0)
+
+
+def _alone_vs_mix(binding, pool, reqs):
     with binding.Server(hbm_budget_bytes=1 << 29, num_streams=3, max_batch=32, alone_min_keys=1 << 18) as srv:
         alone = []
         for r in reqs:                            # one at a time: each runs alone
@@ -135,7 +145,7 @@ def test_injected_fault_fails_only_its_ticket():
     assert st[5] == AP_ERR_DEVICE and all(s == AP_OK for i, s in enumerate(st) if i != 5)
     for i in range(12):
         if i != 5:
-            assert np.array_equal(to_host(outs[i]), np.sort(pool.host["d"][i * 1000:(i + 1) * 1000]))
+            assert np.array_equal(to_host(outs[i]), oracle.sort_u32(pool.host["d"][i * 1000:(i + 1) * 1000]))
 
 
 def test_edge_requests_in_place_empty_tiny():
