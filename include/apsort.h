@@ -103,6 +103,27 @@ ap_status ap_sort_u32_ws(const uint32_t *d_in, uint32_t *d_out, size_t n, int P,
                          void *stream);
 
 /*
+ * ap_sort_u32_noalloc -- ap_sort_u32 for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as ap_sort_u32, with
+ * n <= AP_NOALLOC_MAX_KEYS (larger n: AP_ERR_INVALID, nothing enqueued).
+ *
+ * Its scratch is a fixed 26 MiB array in the library's device memory, which
+ * every GPU the library runs on holds until the process ends.  The call makes
+ * no allocation, no host synchronisation and no memset (the array's control
+ * words are zeroed by a kernel on `stream`), so it can be captured.  All calls
+ * on one device share that array and the previous call's contents are
+ * overwritten: calls that overlap in time on one device (other streams, other
+ * threads) race and must be serialised by the caller.  The rank primitive is
+ * the atomic one only if another entry point has already run the device's
+ * lane-order check (see ap_rank_check_state); otherwise the order-agnostic
+ * rank runs, with identical results.
+ */
+#define AP_NOALLOC_MAX_KEYS ((size_t)1 << 22)
+ap_status ap_sort_u32_noalloc(const uint32_t *d_in, uint32_t *d_out, size_t n,
+                              int P, uint32_t *d_splitters, void *stream);
+
+/*
  * ap_sort_pairs_u32 -- sort (key, value) pairs by key.
  *
  * The same LSD radix sort on the keys (Sec. 3.2 bucketing per digit, Sec.

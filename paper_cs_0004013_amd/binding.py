@@ -37,6 +37,7 @@ SIGNATURES = [
     ("ap_sort_workspace_bytes", _SZ, [_SZ]),
     ("ap_workspace_init", _I, [_VP, _SZ, _VP]),
     ("ap_sort_u32_ws", _I, [_VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
+    ("ap_sort_u32_noalloc", _I, [_VP, _VP, _SZ, _I, _VP, _VP]),
     ("ap_sort_pairs_u32", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP]),
     ("ap_sort_pairs_workspace_bytes", _SZ, [_SZ]),
     ("ap_sort_pairs_u32_ws", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
@@ -146,6 +147,24 @@ def ap_sort_u32(t_in, t_out, P: int = 64, t_splitters=None, stream=None) -> None
     st = lib().ap_sort_u32(_keys_ptr(t_in, "in") if n else None, _keys_ptr(t_out, "out") if n else None, n, P,
                            spl or None, _stream(stream))
     check(st, "ap_sort_u32")
+
+
+NOALLOC_MAX_KEYS = 1 << 22
+
+
+def ap_sort_u32_noalloc(t_in, t_out, P: int = 64, t_splitters=None, stream=None) -> None:
+    """ap_sort_u32 with the library's fixed scratch array (no allocation); n <= 2^22."""
+    n = t_in.numel()
+    if t_out.numel() != n:
+        raise ValueError("input and output sizes differ")
+    spl = None
+    if t_splitters is not None:
+        if t_splitters.numel() < max(P - 1, 0):
+            raise ValueError("splitter tensor needs P-1 entries")
+        spl = _keys_ptr(t_splitters, "splitters")
+    st = lib().ap_sort_u32_noalloc(_keys_ptr(t_in, "in") if n else None, _keys_ptr(t_out, "out") if n else None, n,
+                                   P, spl, _stream(stream))
+    check(st, "ap_sort_u32_noalloc")
 
 
 def ap_sort_pairs_u32(t_keys_in, t_vals_in, t_keys_out, t_vals_out, P: int = 1, t_splitters=None,
