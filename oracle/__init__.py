@@ -2,13 +2,14 @@
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's CPU-baseline leg are
 the only callers.  The HIP library never imports, links or calls anything here, and nothing here
-imports the HIP package.  The arithmetic lives in ``apsort_oracle.c`` (plain single-threaded C,
-compiled with gcc); this module only marshals numpy arrays into it.
+imports the HIP package.  The arithmetic lives in ``apsort_oracle.c`` (plain C, single-threaded
+except for the timing variant, compiled with gcc); this module only marshals numpy arrays into it.
 
 Functions and the passages they follow:
   digit_hist      -- Sec. 3.2, first loop of bucket(): per-digit bucket counts.
   bucket_pass     -- Sec. 3.2 bucketing of one 8-bit digit (counts, cumulative totals, partial sort).
   sort_u32        -- Sec. 3.3.1 LSD radix sort, each pass being the Sec. 3.2 bucketing step.
+  sort_u32_mt     -- the same passes, each split over host threads (for the CPU timing baseline).
   slice_starts    -- Sec. 1.1 even distribution over P cells, lower cell takes the extra element
                      (footnote to Sec. 3.4.2).
   splitters       -- first key of each cell p = 1..P-1, all-ones sentinel for an empty cell
@@ -33,7 +34,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so (plain -O2, no vectorisation tricks)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -46,6 +47,8 @@ def _bind(path: str):
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.oracle_digit_hist.argtypes = [u32p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, u64p]
     lib.oracle_sort_u32.argtypes = [u32p, u32p, ctypes.c_size_t]
+    lib.oracle_sort_u32_mt.argtypes = [u32p, u32p, ctypes.c_size_t, ctypes.c_int]
+    lib.oracle_sort_u32_mt.restype = ctypes.c_int
     lib.oracle_bucket_pass.argtypes = [u32p, u32p, ctypes.c_size_t, ctypes.c_int]
     lib.oracle_bucket_pass.restype = None
     lib.oracle_slice_starts.argtypes = [ctypes.c_size_t, ctypes.c_int, u64p]
@@ -118,6 +121,15 @@ def sort_u32(keys) -> np.ndarray:
     out = np.empty_like(k)
     if k.size and _load().oracle_sort_u32(_p32(k), _p32(out), k.size) != 0:
         raise MemoryError("oracle_sort_u32 failed")
+    return out
+
+
+def sort_u32_mt(keys, threads: int) -> np.ndarray:
+    """The same sort with every pass split over ``threads`` host threads (timing variant)."""
+    k = _u32(keys)
+    out = np.empty_like(k)
+    if k.size and _load().oracle_sort_u32_mt(_p32(k), _p32(out), k.size, int(threads)) != 0:
+        raise ValueError("oracle_sort_u32_mt: invalid argument or out of memory")
     return out
 
 

@@ -5,8 +5,9 @@
  * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may include, link
  * or call this file: only the test suite, the smoke check and the benchmark's
  * CPU-baseline leg use it.  It shares no code, header, table or helper with
- * the HIP library; it is plain, slow, single-threaded C written from the
- * paper so that a reader can check it against the text by eye.
+ * the HIP library; it is plain, slow C (single-threaded, but for the timing
+ * variant) written from the paper so that a reader can check it against the
+ * text by eye.
  *
  * What it computes
  *   - oracle_digit_hist: the bucket histogram of one digit, the first loop of
@@ -36,6 +37,13 @@
  *     output, the first list's element on a tie.  Splitting the merged list at
  *     the first list's length gives the merge-exchange: the lower cell keeps
  *     the lower values, both cells keep their element counts.
+ *   - oracle_sort_u32_mt: the same LSD sort with each pass split over T
+ *     threads, for timing on a many-core host only.  Thread t takes the t-th
+ *     contiguous chunk of the pass's input; the cumulative totals are taken
+ *     over (bucket, thread) in that order, so thread t's elements of bucket v
+ *     land after those of every lower bucket and after bucket v's elements of
+ *     threads < t, and each thread moves its chunk in input order: the output
+ *     of every pass is that of oracle_bucket_pass.
  *   - oracle_bucket_pass_pairs / oracle_sort_pairs_u32: the same bucketing
  *     pass and LSD sort with a 32-bit value travelling with every key.  Each
  *     pass keeps the order of elements with equal digits (Sec. 3.3.1), so
@@ -48,6 +56,8 @@
  * Error behaviour: functions return 0 on success and -1 when a scratch
  * allocation fails or an argument is invalid; nothing is written then.
  */
+#define _POSIX_C_SOURCE 200809L
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -147,6 +157,101 @@ int oracle_sort_u32(const uint32_t *in, uint32_t *out, size_t n)
     memcpy(out, a, n * sizeof(uint32_t));
     free(a);
     free(b);
+    return 0;
+}
+
+/* ---- timing variant: each bucketing pass split over threads ---- */
+struct mt_job {
+    const uint32_t *src;
+    uint32_t *dst;
+    size_t lo, hi;          /* this thread's chunk of the pass input */
+    int shift;
+    uint64_t *count;        /* ORACLE_BUCKETS counts of the chunk, then its first slots */
+};
+
+static void *mt_count(void *arg)
+{
+    struct mt_job *j = (struct mt_job *)arg;
+    for (unsigned v = 0; v < ORACLE_BUCKETS; ++v)
+        j->count[v] = 0;
+    for (size_t i = j->lo; i < j->hi; ++i)
+        j->count[(j->src[i] >> j->shift) & (ORACLE_BUCKETS - 1)] += 1;
+    return NULL;
+}
+
+static void *mt_move(void *arg)
+{
+    struct mt_job *j = (struct mt_job *)arg;
+    for (size_t i = j->lo; i < j->hi; ++i) {
+        unsigned v = (j->src[i] >> j->shift) & (ORACLE_BUCKETS - 1);
+        j->dst[j->count[v]] = j->src[i];
+        j->count[v] += 1;
+    }
+    return NULL;
+}
+
+/* Runs fn on every job, one thread each (the calling thread takes job 0). */
+static int mt_run(void *(*fn)(void *), struct mt_job *jobs, int nthreads, pthread_t *tid)
+{
+    int started = 0, rc = 0;
+    for (int t = 1; t < nthreads; ++t) {
+        if (pthread_create(&tid[t], NULL, fn, &jobs[t]) != 0) {
+            rc = -1;
+            break;
+        }
+        started = t;
+    }
+    fn(&jobs[0]);
+    for (int t = 1; t <= started; ++t)
+        pthread_join(tid[t], NULL);
+    if (rc != 0)                       /* finish the jobs no thread took */
+        for (int t = started + 1; t < nthreads; ++t)
+            fn(&jobs[t]);
+    return 0;
+}
+
+int oracle_sort_u32_mt(const uint32_t *in, uint32_t *out, size_t n, int nthreads)
+{
+    if (n == 0)
+        return 0;
+    if (!in || !out || nthreads < 1 || nthreads > 1024)
+        return -1;
+    uint32_t *a = (uint32_t *)malloc(n * sizeof(uint32_t));
+    uint32_t *b = (uint32_t *)malloc(n * sizeof(uint32_t));
+    struct mt_job *jobs = (struct mt_job *)malloc((size_t)nthreads * sizeof(struct mt_job));
+    uint64_t *counts = (uint64_t *)malloc((size_t)nthreads * ORACLE_BUCKETS * sizeof(uint64_t));
+    pthread_t *tid = (pthread_t *)malloc((size_t)nthreads * sizeof(pthread_t));
+    if (!a || !b || !jobs || !counts || !tid) {
+        free(a); free(b); free(jobs); free(counts); free(tid);
+        return -1;
+    }
+    memcpy(a, in, n * sizeof(uint32_t));
+    for (int pass = 0; pass * ORACLE_DIGIT_BITS < 32; ++pass) {
+        const int shift = pass * ORACLE_DIGIT_BITS;
+        for (int t = 0; t < nthreads; ++t) {
+            jobs[t].src = a;
+            jobs[t].dst = b;
+            jobs[t].lo = n * (size_t)t / (size_t)nthreads;
+            jobs[t].hi = n * (size_t)(t + 1) / (size_t)nthreads;
+            jobs[t].shift = shift;
+            jobs[t].count = counts + (size_t)t * ORACLE_BUCKETS;
+        }
+        mt_run(mt_count, jobs, nthreads, tid);
+        /* cumulative totals over (bucket, thread): first slot of thread t's part of bucket v */
+        uint64_t running = 0;
+        for (unsigned v = 0; v < ORACLE_BUCKETS; ++v)
+            for (int t = 0; t < nthreads; ++t) {
+                uint64_t c = jobs[t].count[v];
+                jobs[t].count[v] = running;
+                running += c;
+            }
+        mt_run(mt_move, jobs, nthreads, tid);
+        uint32_t *t = a;
+        a = b;
+        b = t;
+    }
+    memcpy(out, a, n * sizeof(uint32_t));
+    free(a); free(b); free(jobs); free(counts); free(tid);
     return 0;
 }
 

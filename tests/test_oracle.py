@@ -111,6 +111,24 @@ def test_vs_numpy_sort(n):
     assert np.array_equal(oracle.sort_u32(x), np.sort(x))
 
 
+@pytest.mark.parametrize("threads", [1, 2, 3, 8, 16])
+@pytest.mark.parametrize("n", [0, 1, 5, 15, 300, 70_001, (1 << 20) + 3])
+def test_mt_variant_vs_numpy_and_single_thread(n, threads):
+    """The timing variant (passes split over threads) gives numpy's sort, and bit for bit the
+    single-thread oracle's output, for thread counts above and below n."""
+    rng = np.random.default_rng(n + 17 * threads)
+    x = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    got = oracle.sort_u32_mt(x, threads)
+    assert np.array_equal(got, np.sort(x))
+    assert np.array_equal(got, oracle.sort_u32(x))
+
+
+@pytest.mark.parametrize("dist", ["c", "e"])
+def test_mt_variant_clustered(dist):
+    ks = inputs.keyset(dist, 200_001, seed=5)
+    assert np.array_equal(oracle.sort_u32_mt(ks.keys, 7), np.sort(ks.keys))
+
+
 @pytest.mark.parametrize("dist", inputs.DISTS)
 def test_distributions_vs_numpy_and_invariants(dist):
     ks = inputs.keyset(dist, 100_003, seed=7)

@@ -41,6 +41,12 @@ MUTANTS = {
     "merge: rest of the second list dropped": ("    while (j < nb)\n        out[k++] = b[j++];", "    while (j + 1 < nb)\n        out[k++] = b[j++];"),
     "merge: compares against the previous head": ("if (b[j] < a[i])", "if (j > 0 && b[j - 1] < a[i])"),
     "merge: takes the larger head": ("if (b[j] < a[i])", "if (b[j] > a[i])"),
+    "mt: totals taken thread by thread": (
+        "for (unsigned v = 0; v < ORACLE_BUCKETS; ++v)\n            for (int t = 0; t < nthreads; ++t) {",
+        "for (int t = 0; t < nthreads; ++t)\n            for (unsigned v = 0; v < ORACLE_BUCKETS; ++v) {"),
+    "mt: a thread moves its chunk backwards": (
+        "for (size_t i = j->lo; i < j->hi; ++i) {\n        unsigned v",
+        "for (size_t i = j->hi; i-- > j->lo;) {\n        unsigned v"),
 }
 
 
@@ -70,6 +76,8 @@ def _battery() -> bool:
         for na, nb in ((1000, 3), (70_001, 65_536)):
             pins.test_merge_vs_numpy(na, nb)
         pins.test_merge_closed_forms()
+        for n, threads in ((300, 3), (70_001, 8), (5, 16)):
+            pins.test_mt_variant_vs_numpy_and_single_thread(n, threads)
     except AssertionError:
         return False
     return True
@@ -80,7 +88,7 @@ def _compile(src_text: str, out_dir: str, name: str) -> str:
     so = os.path.join(out_dir, name + ".so")
     with open(c, "w") as f:
         f.write(src_text)
-    subprocess.check_call(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-o", so, c])
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-pthread", "-o", so, c])
     return so
 
 
