@@ -7,14 +7,17 @@ into P = 64 cells; `value` is keys sorted per second over the K timed steps (Gke
 
 `roofline` describes the digit-pass kernel k_pass: algorithmic bytes per launch (8 B per key) over
 the mean launch duration, timed with HIP events recorded around each launch on the sort's stream
-during the timed steps.  `traffic` comes from the committed rocprofv3 counter summary when it was
-taken on the current kernel source.
+(in a second loop of the same sorts right after the timed steps: the events cost time of their
+own).  `traffic` and the rocprofv3 mean duration come from the committed profile summary when it
+was taken on the current kernel source.
 
 Extra fields (each can be skipped): the other distributions (b)-(e) at 2^26 and the adversarial
-2^27 set; the 4096-segment batch (lengths log-uniform in [64, 2^18]) sorted by the batched
-segmented form vs a loop of plain per-array launches; the served form (Poisson arrivals of
-log-uniform [2^10, 2^24] requests at several rates) vs one plain launch per request, FIFO on one
-stream; p50/p99 latency of a 2^20-key sort.  The CPU baseline is the oracle (plain C LSD radix
+2^27 set; the per-pass roofline at 2^27 uniform keys (twice the size of the 256 MB memory-side
+cache); the 4096-segment batch (lengths log-uniform in [64, 2^18]) sorted by the batched segmented
+form vs a loop of plain per-array launches; the served form: 100k requests (Poisson arrivals,
+log-uniform [2^10, 2^24] keys) at swept rates vs one plain launch per request, FIFO on one stream,
+every output checked on the device (order + multiset hash) and a seeded 1% sample against the
+oracle; p50/p99 latency of a 2^20-key sort.  The CPU baseline is the oracle (plain C LSD radix
 sort) on the same 2^26 keys, single-threaded and with every pass split over the host's threads.
 """
 from __future__ import annotations
@@ -32,8 +35,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Gkeys/s on 64M u32 & 4096-segment batch; % HBM roofline; p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
 N_MAIN = 1 << 26
-# the pass kernel and the device helpers it inlines (rank, look-back words)
-KERNEL_SRCS = [os.path.join(ROOT, "paper_cs_0004013_amd", "csrc", f) for f in ("apsort_kernels.h", "apsort_device.h")]
+# the pass kernel, its tile core and the device helpers it inlines (rank, look-back words)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_cs_0004013_amd", "csrc", f)
+               for f in ("apsort_kernels.h", "apsort_pass_core.h", "apsort_device.h")]
 COUNTERS = os.path.join(ROOT, "profiles", "k_pass_counters_uniform_2p26.md")
 
 
@@ -41,9 +45,9 @@ def kernel_sha() -> str:
     return hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRCS)).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per k_pass launch from the committed rocprofv3 counter summary, or None when the
-    summary is missing or was taken on a different kernel source."""
+def read_profile() -> dict | None:
+    """HBM bytes and mean duration per k_pass launch from the committed rocprofv3 summary, or None
+    when the summary is missing or was taken on a different kernel source."""
     if not os.path.exists(COUNTERS):
         return None
     vals = {}
@@ -55,7 +59,7 @@ def read_traffic():
     if vals.get("kernel_source_sha") != kernel_sha():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return {"traffic": float(vals["hbm_bytes_per_launch"]), "mean_us": float(vals["mean_duration_us"])}
     except (KeyError, ValueError):
         return None
 
@@ -83,6 +87,14 @@ def time_sorts(binding, torch, t_in, t_out, spl, steps: int, warmup: int, profil
     return dt, prof
 
 
+def pass_stats(binding, prof):
+    """Mean duration (s) of the digit-pass launches that ran, from HIP-event records."""
+    ms, launches = prof
+    pass_ms = sum(ms[binding.AP_KIND_PASS + d] for d in range(4))
+    n = sum(launches[binding.AP_KIND_PASS + d] for d in range(4))
+    return pass_ms / max(n, 1) / 1e3
+
+
 def pct(v, p):
     import numpy as np
     return float(np.percentile(np.asarray(v, dtype=np.float64), p)) if len(v) else None
@@ -108,6 +120,49 @@ def leg_latency(binding, torch, np, inputs):
             "gkeys_s_p50": round((1 << 20) / pct(ms, 50) / 1e6, 2)}
 
 
+def leg_pass_2p27(binding, torch, np, inputs, spl):
+    """Per-pass roofline at 2^27 uniform keys (seed 7): 1 GiB of keys per pass, four times the
+    memory-side cache, so no pass can be served from it."""
+    n = 1 << 27
+    t_in = torch.from_numpy(inputs.keyset("a", n, seed=7).keys.view(np.int32)).to("cuda")
+    t_out = torch.empty_like(t_in)
+    dt, _ = time_sorts(binding, torch, t_in, t_out, spl, 10, 3, False)
+    _, prof = time_sorts(binding, torch, t_in, t_out, spl, 10, 1, True)
+    pass_s = pass_stats(binding, prof)
+    gbs = 8 * n / pass_s / 1e9
+    return {"n": n, "ms_per_sort": round(dt * 1e3 / 10, 4), "gkeys_s": round(n * 10 / dt / 1e9, 3),
+            "pass_us": round(pass_s * 1e6, 2), "pass_gbs": round(gbs, 1),
+            "pass_frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def leg_msd(binding, torch, np, pools, spl, steps: int = 10):
+    """The bucketing variant (top 16 bits, then a local sort per bucket) against the LSD sort on
+    the same 2^26 keys, distributions (a) and (e); outputs compared with the LSD sort's."""
+    res = {}
+    for dist in ("a", "e"):
+        if dist not in pools:
+            continue
+        t_in = pools[dist]
+        n = t_in.numel()
+        out_m, out_l = torch.empty_like(t_in), torch.empty_like(t_in)
+        times = {}
+        for name, fn, out in (("msd", binding.ap_sort_u32_msd, out_m), ("lsd", binding.ap_sort_u32, out_l)):
+            for _ in range(3):
+                fn(t_in, out, 64, spl)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                fn(t_in, out, 64, spl)
+            e1.record()
+            torch.cuda.synchronize()
+            times[name] = e0.elapsed_time(e1) / steps
+        res[dist] = {"msd_ms": round(times["msd"], 4), "msd_gkeys_s": round(n / times["msd"] / 1e6, 3),
+                     "lsd_ms": round(times["lsd"], 4), "lsd_gkeys_s": round(n / times["lsd"] / 1e6, 3),
+                     "same_output": bool(torch.equal(out_m, out_l))}
+    return res
+
+
 def leg_pairs(binding, torch, np, inputs, t_keys, steps: int = 10):
     """(key, value) pairs: the same 2^26 uniform keys with values 0..n-1 (an argsort); per-pass
     time from HIP events, 16 algorithmic bytes per key per pass (key and value, read and write)."""
@@ -129,9 +184,7 @@ def leg_pairs(binding, torch, np, inputs, t_keys, steps: int = 10):
         binding.ap_sort_pairs_u32(t_keys, vals, k_out, v_out, 64, None)
     torch.cuda.synchronize()
     binding.ap_profile_enable(False)
-    ms, cnt = binding.ap_profile_read()
-    npass = sum(cnt[binding.AP_KIND_PASS + d] for d in range(4))
-    pass_us = sum(ms[binding.AP_KIND_PASS + d] for d in range(4)) / max(npass, 1) * 1e3
+    pass_us = pass_stats(binding, binding.ap_profile_read()) * 1e6
     return {"n": n, "ms_per_sort": round(dt * 1e3, 4), "gpairs_s": round(n / dt / 1e9, 3),
             "pass_us": round(pass_us, 2), "pass_gbs": round(16 * n / pass_us / 1e3, 1),
             "pass_frac_of_8tbs": round(16 * n / pass_us / 1e3 / HBM_PEAK_GBS, 4)}
@@ -159,8 +212,26 @@ def leg_merge(binding, torch, np, inputs, t_keys, steps: int = 10):
             "frac_of_8tbs": round(8 * n / ms / 1e6 / HBM_PEAK_GBS, 4), "ok": ok}
 
 
+def check_arrays(binding, torch, np, base_ptr: int, offsets, stream=None):
+    """Device check of the arrays [offsets[s], offsets[s+1]) of the int32 buffer at base_ptr:
+    (descents, SplitMix64 sum, xor) per array, as a (nseg, 3) uint64 numpy array."""
+    off = np.asarray(offsets, dtype=np.int64)
+    nseg = off.size - 1
+    ptrs = torch.from_numpy(base_ptr + 4 * off[:-1]).to("cuda")
+    cnts = torch.from_numpy(np.diff(off)).to("cuda")
+    acc = torch.zeros((nseg, 3), dtype=torch.int64, device="cuda")
+    for s0 in range(0, nseg, 4096):
+        c = min(4096, nseg - s0)
+        binding.ap_check_u32_batch(ptrs.data_ptr() + 8 * s0, cnts.data_ptr() + 8 * s0, c, int(np.diff(off).max()),
+                                   acc.data_ptr() + 24 * s0, stream)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy().view(np.uint64)
+
+
 def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True):
-    """4096 segments, lengths log-uniform in [64, 2^18] (seed 0); segment s uses seed s."""
+    """4096 segments, lengths log-uniform in [64, 2^18] (seed 0); segment s uses seed s.  Every
+    segment of the result is checked on the device: no descent, and the SplitMix64 multiset hash
+    of the segment's input."""
     L = inputs.segment_lengths(4096, seed=0)
     keys, off, _ = inputs.segment_keys(L)
     n = int(keys.size)
@@ -180,17 +251,15 @@ def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True)
             s.synchronize()
             if i >= 2:
                 ms.append(a.elapsed_time(b))
-        got = t_work.cpu().numpy().view(np.uint32)
-        # cheap full check: nondecreasing inside every segment, multiset kept per segment boundary
-        d = np.diff(got.astype(np.int64))
-        inside = np.ones(n - 1, dtype=bool)
-        inside[off[1:-1].astype(np.int64) - 1] = False
-        ok = bool(np.all(d[inside] >= 0)) and int(got.astype(np.uint64).sum()) == int(keys.astype(np.uint64).sum())
+        h_in = check_arrays(binding, torch, np, t_src.data_ptr(), off)
+        h_out = check_arrays(binding, torch, np, t_work.data_ptr(), off)
+        bad = int(np.count_nonzero((h_out[:, 0] != 0) | np.any(h_out[:, 1:] != h_in[:, 1:], axis=1)))
         res["segments"] = 4096
         res["keys"] = n
         res["batched_ms_p50"] = round(pct(ms, 50), 4)
         res["batched_gkeys_s"] = round(n / pct(ms, 50) / 1e6, 3)
-        res["batched_ok"] = ok
+        res["segments_bad"] = bad
+        res["batched_ok"] = bad == 0
         if not baseline:
             return res
         # baseline: one plain ap_sort_u32 per segment, in order, on the same stream
@@ -217,108 +286,278 @@ def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True)
     return res
 
 
-def leg_served(binding, torch, np, inputs, pools_dev, nreq: int, rates, alone_min_keys: int = 1 << 16):
-    """Poisson trace of nreq requests (sizes log-uniform [2^10, 2^24], distribution and pool
-    window by request seed) served by the request server at several offered rates, and the same
-    trace as one plain launch per request, FIFO on one stream."""
-    pool_keys = int(next(iter(pools_dev.values())).numel())
-    ring = 128                                 # output buffers reused round-robin
-    outs = [torch.empty(1 << 24, dtype=torch.int32, device="cuda") for _ in range(ring)]
-    spls = [torch.empty(63, dtype=torch.int32, device="cuda") for _ in range(ring)]
-    lib = binding.lib()
-    res = {"requests": nreq, "pool_keys": pool_keys}
-
-    # -- baseline: plain launches back to back (closed loop) gives the capacity, then its latency
-    base_trace = inputs.request_trace(nreq, rate_per_s=1.0, pool_keys=pool_keys, seed=0)
-    total_keys = sum(r.n for r in base_trace)
+def leg_segmented_long(binding, torch, np, inputs, spl, steps: int = 5):
+    """Long segments through the device-wide passes: (i) 4 segments of 2^24 uniform keys among
+    4092 log-uniform short ones ([64, 2^14], seed 3), (ii) one segment of 2^28 uniform keys; each
+    against ap_sort_u32 of the same keys as one array.  Checked on the device per segment."""
+    rng = np.random.default_rng(5)
+    short = inputs.segment_lengths(4092, seed=3, lo=64, hi=1 << 14)
+    L = np.concatenate([[1 << 24] * 4, short]).astype(np.int64)
+    L = L[rng.permutation(L.size)]
+    off_a = np.zeros(L.size + 1, np.int64)
+    np.cumsum(L, out=off_a[1:])
+    res = {"long_min": binding.ap_segmented_get_long_min()}
+    cases = [("four_2p24_plus_4092_short", inputs.keyset("a", int(off_a[-1]), seed=11).keys, off_a),
+             ("one_2p28", inputs.keyset("a", 1 << 28, seed=12).keys, np.array([0, 1 << 28], np.int64))]
     s = torch.cuda.Stream()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nreq)]
-    start = torch.cuda.Event(enable_timing=True)
-    start.record(s)
-    t0 = time.perf_counter()
-    for i, r in enumerate(base_trace):
-        src = pools_dev[r.dist][r.pool_offset:r.pool_offset + r.n]
-        st = lib.ap_sort_u32(src.data_ptr(), outs[i % ring].data_ptr(), r.n, 64, spls[i % ring].data_ptr(),
-                             s.cuda_stream)
-        if st:
-            raise RuntimeError(binding.last_error())
-        evs[i].record(s)
-    s.synchronize()
-    t_plain = time.perf_counter() - t0
-    plain_cap = nreq / t_plain
-    res["plain_fifo_closed_loop"] = {"req_s": round(plain_cap, 1), "gkeys_s": round(total_keys / t_plain / 1e9, 3)}
-
-    # -- served, open loop at rates relative to the plain capacity; plain FIFO at the same rates
-    def run_served(srv, tr):
-        st0 = srv.stats(reset_latencies=True)
-        tickets = [0] * nreq
-        t0 = time.perf_counter()
-        for i, r in enumerate(tr):
-            while time.perf_counter() - t0 < r.arrival_s:
-                pass
-            if i >= ring:
-                st = srv.wait(tickets[i - ring])  # output buffer reuse
-                if st:
-                    raise RuntimeError(f"request failed: {st}")
-            src = pools_dev[r.dist][r.pool_offset:r.pool_offset + r.n]
-            tickets[i] = srv.submit_ptr(src.data_ptr(), outs[i % ring].data_ptr(), r.n, 64,
-                                        spls[i % ring].data_ptr())
-        for i in range(max(0, nreq - ring), nreq):
-            st = srv.wait(tickets[i])
-            if st:
-                raise RuntimeError(f"request failed: {st}")
-        wall = time.perf_counter() - t0
-        stt = srv.stats(reset_latencies=True)
-        # the last `ring` outputs are still in place: compare them with torch's sort of the input
-        # window (keys < 2^31, so int32 order is the unsigned order), after the timed region
-        checked, bad = 0, 0
-        for i in range(max(0, nreq - ring), nreq):
-            r = tr[i]
-            src = pools_dev[r.dist][r.pool_offset:r.pool_offset + r.n]
-            want = torch.sort(src)[0]
-            bad += int(not torch.equal(outs[i % ring][:r.n], want))
-            checked += 1
-        return {"gkeys_s": round(sum(r.n for r in tr) / wall / 1e9, 3), "p50_ms": round(stt["p50_us"] / 1e3, 4),
-                "p99_ms": round(stt["p99_us"] / 1e3, 4), "batches": stt["batches"] - st0["batches"],
-                "alone": stt["alone"] - st0["alone"], "outputs_checked": checked, "outputs_bad": bad}
-
-    res["points"] = []
-    res["alone_min_keys"] = alone_min_keys
-    with binding.Server(hbm_budget_bytes=64 << 30, num_streams=4, max_batch=256, alone_min_keys=alone_min_keys) as srv:
-        for frac in rates:
-            lam = frac * plain_cap
-            tr = inputs.request_trace(nreq, rate_per_s=lam, pool_keys=pool_keys, seed=0)
-            served = run_served(srv, tr)
-            # plain FIFO at the same offered rate: latency = completion event - arrival
-            start = torch.cuda.Event(enable_timing=True)
-            t1 = time.perf_counter()
-            start.record(s)
-            for i, r in enumerate(tr):
-                while time.perf_counter() - t1 < r.arrival_s:
-                    pass
-                src = pools_dev[r.dist][r.pool_offset:r.pool_offset + r.n]
-                lib.ap_sort_u32(src.data_ptr(), outs[i % ring].data_ptr(), r.n, 64, spls[i % ring].data_ptr(),
-                                s.cuda_stream)
-                evs[i].record(s)
+    for name, keys, off in cases:
+        n = int(keys.size)
+        with torch.cuda.stream(s):
+            t_src = torch.from_numpy(keys.view(np.int32)).to("cuda")
+            t_work = torch.empty_like(t_src)
+            t_off = torch.from_numpy(off.astype(np.uint32).view(np.int32)).to("cuda")
+            ms = []
+            for i in range(steps + 2):
+                t_work.copy_(t_src)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s)
+                binding.ap_sort_u32_segmented(t_work, t_off, stream=s)
+                b.record(s)
+                s.synchronize()
+                if i >= 2:
+                    ms.append(a.elapsed_time(b))
+            h_in = check_arrays(binding, torch, np, t_src.data_ptr(), off)
+            h_out = check_arrays(binding, torch, np, t_work.data_ptr(), off)
+            bad = int(np.count_nonzero((h_out[:, 0] != 0) | np.any(h_out[:, 1:] != h_in[:, 1:], axis=1)))
+            t_out = torch.empty_like(t_src)
+            for _ in range(2):
+                binding.ap_sort_u32(t_src, t_out, 1, None, stream=s)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(steps):
+                binding.ap_sort_u32(t_src, t_out, 1, None, stream=s)
+            e1.record(s)
             s.synchronize()
-            wall_p = time.perf_counter() - t1
-            lat_p = [start.elapsed_time(evs[i]) - tr[i].arrival_s * 1e3 for i in range(nreq)]
-            res["points"].append({
-                "offered_frac_of_plain_capacity": frac,
-                "offered_req_s": round(lam, 1),
-                "served": served,
-                "plain_fifo": {"gkeys_s": round(sum(r.n for r in tr) / wall_p / 1e9, 3),
-                               "p50_ms": round(pct(lat_p, 50), 4), "p99_ms": round(pct(lat_p, 99), 4)},
-            })
-            log(f"served frac={frac}: {res['points'][-1]}")
-    # a 1 GiB budget (256 MiB of scratch per slot) so that admission binds, at 1.25x
-    with binding.Server(hbm_budget_bytes=1 << 30, num_streams=4, max_batch=256, alone_min_keys=alone_min_keys) as srv:
-        tr = inputs.request_trace(nreq, rate_per_s=1.25 * plain_cap, pool_keys=pool_keys, seed=0)
-        res["budget_1GiB_at_1.25"] = run_served(srv, tr)
-        log(f"served 1 GiB budget: {res['budget_1GiB_at_1.25']}")
+            plain = e0.elapsed_time(e1) / steps
+            seg = pct(ms, 50)
+            res[name] = {"keys": n, "segments": int(off.size - 1), "segmented_ms_p50": round(seg, 4),
+                         "segmented_gkeys_s": round(n / seg / 1e6, 3), "plain_sort_ms": round(plain, 4),
+                         "plain_sort_gkeys_s": round(n / plain / 1e6, 3), "ratio": round(plain / seg, 3),
+                         "segments_bad": bad}
+            del t_src, t_work, t_out
     return res
 
 
+# ------------------------------------------------------------------------------------------------
+class ServedTrace:
+    """The served workload: nreq requests, request r drawing its size (log-uniform [2^10, 2^24]),
+    distribution and window into that distribution's device-resident pool from seed r.  Sizes,
+    windows and inputs do not depend on the arrival rate, so the input hashes and the oracle's
+    results for the seeded 1% sample are computed once and serve every rate point."""
+
+    RING = 256            # output buffers of 2^24 keys, reused round-robin
+    CAP = 1 << 24
+    BATCH = 64            # outputs checked per device check launch
+
+    def __init__(self, binding, torch, np, inputs, pools_dev, pools_host, nreq: int):
+        import oracle
+        self.b, self.torch, self.np, self.inputs = binding, torch, np, inputs
+        self.nreq = nreq
+        self.pool_keys = int(next(iter(pools_dev.values())).numel())
+        self.tr = inputs.request_trace(nreq, rate_per_s=1.0, pool_keys=self.pool_keys, seed=0)
+        self.n = np.array([r.n for r in self.tr], dtype=np.int64)
+        self.total_keys = int(self.n.sum())
+        self.ring = torch.empty(self.RING * self.CAP, dtype=torch.int32, device="cuda")
+        self.spl_ring = torch.empty(self.RING * 64, dtype=torch.int32, device="cuda")
+        slot = np.arange(nreq) % self.RING
+        self.src = np.array([pools_dev[r.dist].data_ptr() + 4 * r.pool_offset for r in self.tr], dtype=np.int64)
+        self.out = self.ring.data_ptr() + 4 * self.CAP * slot
+        self.spl = self.spl_ring.data_ptr() + 4 * 64 * slot
+        self.d_out = torch.from_numpy(self.out).to("cuda")
+        self.d_n = torch.from_numpy(self.n).to("cuda")
+        nb = (nreq + self.BATCH - 1) // self.BATCH
+        self.batch_max = np.array([self.n[k * self.BATCH:(k + 1) * self.BATCH].max() for k in range(nb)])
+        d_src = torch.from_numpy(self.src).to("cuda")
+        self.acc_in = torch.zeros((nreq, 3), dtype=torch.int64, device="cuda")
+        for j0 in range(0, nreq, 4096):
+            c = min(4096, nreq - j0)
+            binding.ap_check_u32_batch(d_src.data_ptr() + 8 * j0, self.d_n.data_ptr() + 8 * j0, c,
+                                       int(self.n[j0:j0 + c].max()), self.acc_in.data_ptr() + 24 * j0)
+        # seeded 1% sample: expected outputs and splitters from the oracle (its timing variant,
+        # pinned bit-exact to the single-thread oracle), kept on the device
+        self.sample = np.sort(inputs.rng_for(4242).choice(nreq, max(1, nreq // 100), replace=False))
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        exp_off = np.zeros(self.sample.size + 1, dtype=np.int64)
+        np.cumsum(self.n[self.sample], out=exp_off[1:])
+        exp = np.empty(int(exp_off[-1]), dtype=np.uint32)
+        exp_spl = np.empty((self.sample.size, 63), dtype=np.uint32)
+        for k, r in enumerate(self.sample):
+            q = self.tr[r]
+            w = oracle.sort_u32_mt(pools_host[q.dist][q.pool_offset:q.pool_offset + q.n], threads)
+            exp[exp_off[k]:exp_off[k + 1]] = w
+            exp_spl[k] = oracle.splitters(w, 64)
+        self.exp = torch.from_numpy(exp.view(np.int32)).to("cuda")
+        self.exp_spl = torch.from_numpy(exp_spl.view(np.int32)).to("cuda")
+        self.exp_off = exp_off
+        self.sample_pos = {int(r): k for k, r in enumerate(self.sample)}
+        self.sample_keys = int(exp_off[-1])
+
+    def arrivals(self, rate: float):
+        tr = self.inputs.request_trace(self.nreq, rate_per_s=rate, pool_keys=self.pool_keys, seed=0)
+        return self.np.array([r.arrival_s for r in tr], dtype=self.np.float64)
+
+    def check_batch(self, k: int, acc, mism, stream):
+        """Device check of the outputs of requests [k*BATCH, (k+1)*BATCH) on `stream`, and the
+        bit-exact comparison of the sampled ones with the oracle's outputs."""
+        torch = self.torch
+        j0, j1 = k * self.BATCH, min((k + 1) * self.BATCH, self.nreq)
+        # max_n sizes the launch (workgroups per array): the batch's own longest request
+        self.b.ap_check_u32_batch(self.d_out.data_ptr() + 8 * j0, self.d_n.data_ptr() + 8 * j0, j1 - j0,
+                                  int(self.batch_max[k]), acc.data_ptr() + 24 * j0, stream)
+        hits = [j for j in range(j0, j1) if j in self.sample_pos]
+        if hits:
+            with torch.cuda.stream(stream):
+                for j in hits:
+                    s, n = self.sample_pos[j], int(self.n[j])
+                    b = j % self.RING
+                    got = self.ring[b * self.CAP: b * self.CAP + n]
+                    mism[0] += (got != self.exp[self.exp_off[s]:self.exp_off[s] + n]).sum()
+                    mism[1] += (self.spl_ring[b * 64: b * 64 + 63] != self.exp_spl[s]).sum()
+
+    def verdict(self, acc, mism) -> dict:
+        np = self.np
+        a = acc.cpu().numpy().view(np.uint64)
+        h = self.acc_in.cpu().numpy().view(np.uint64)
+        bad = int(np.count_nonzero((a[:, 0] != 0) | np.any(a[:, 1:] != h[:, 1:], axis=1)))
+        m = mism.cpu().numpy()
+        return {"outputs_checked": self.nreq, "outputs_bad": bad, "sample_checked": int(self.sample.size),
+                "sample_keys": self.sample_keys, "sample_keys_bad": int(m[0]), "sample_splitters_bad": int(m[1])}
+
+
+def run_served(st: ServedTrace, srv, arr_s) -> dict:
+    """Open loop: request i is submitted at its arrival time with its arrival timestamp (the
+    server measures latency from it); the outputs of whole batches of requests are checked on a
+    side stream RING/2 requests behind, and an output buffer is reused only after its check."""
+    torch, np = st.torch, st.np
+    R, B = st.RING, st.BATCH
+    acc = torch.zeros((st.nreq, 3), dtype=torch.int64, device="cuda")
+    mism = torch.zeros(2, dtype=torch.int64, device="cuda")
+    V = torch.cuda.Stream()
+    nev = R // B + 3
+    evs = [torch.cuda.Event() for _ in range(nev)]
+    tickets = [0] * st.nreq
+    lag = np.zeros(st.nreq)
+    st0 = srv.stats(reset_latencies=True)
+    t0 = time.monotonic_ns() + 2_000_000
+    arr = t0 + (arr_s * 1e9).astype(np.int64)
+    synced = 0                                   # check batches known complete: [0, synced)
+    retired = 0                                  # check batches launched: [0, retired)
+
+    def retire(k):
+        for j in range(k * B, min((k + 1) * B, st.nreq)):
+            s_ = srv.wait(tickets[j])
+            if s_:
+                raise RuntimeError(f"served request {j} failed with status {s_}")
+        st.check_batch(k, acc, mism, V)
+        evs[k % nev].record(V)
+
+    src, out, spl, n = st.src, st.out, st.spl, st.n
+    for i in range(st.nreq):
+        a = int(arr[i])
+        while time.monotonic_ns() < a:
+            pass
+        if i >= R:
+            need = (i - R) // B + 1
+            while synced < need:
+                evs[synced % nev].synchronize()
+                synced += 1
+        tickets[i] = srv.submit_at_ptr(int(src[i]), int(out[i]), int(n[i]), 64, int(spl[i]), a)
+        lag[i] = time.monotonic_ns() - a
+        while (retired + 1) * B <= i + 1 - R // 2:
+            retire(retired)
+            retired += 1
+    while retired * B < st.nreq:
+        retire(retired)
+        retired += 1
+    V.synchronize()
+    wall = (time.monotonic_ns() - t0) / 1e9
+    stt = srv.stats(reset_latencies=True)
+    return {"gkeys_s": round(st.total_keys / wall / 1e9, 3), "p50_ms": round(stt["p50_us"] / 1e3, 4),
+            "p99_ms": round(stt["p99_us"] / 1e3, 4), "latency_from": "arrival",
+            "submit_lag_mean_ms": round(float(lag.mean()) / 1e6, 4),
+            "submit_lag_max_ms": round(float(lag.max()) / 1e6, 3),
+            "batches": stt["batches"] - st0["batches"], "alone": stt["alone"] - st0["alone"],
+            **st.verdict(acc, mism)}
+
+
+def run_plain(st: ServedTrace, arr_s, closed_loop: bool = False) -> dict:
+    """One plain ap_sort_u32 per request, FIFO on one stream, launched at its arrival time (or
+    back to back); latency = completion event - arrival.  The same device checks run on the
+    stream after every BATCH requests."""
+    torch, np = st.torch, st.np
+    lib = st.b.lib()
+    B = st.BATCH
+    acc = torch.zeros((st.nreq, 3), dtype=torch.int64, device="cuda")
+    mism = torch.zeros(2, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(st.nreq)]
+    start = torch.cuda.Event(enable_timing=True)
+    sid = s.cuda_stream
+    src, out, spl, n = st.src, st.out, st.spl, st.n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(s)
+    for i in range(st.nreq):
+        if not closed_loop:
+            a = float(arr_s[i])
+            while time.perf_counter() - t0 < a:
+                pass
+        r = lib.ap_sort_u32(int(src[i]), int(out[i]), int(n[i]), 64, int(spl[i]), sid)
+        if r:
+            raise RuntimeError(st.b.last_error())
+        evs[i].record(s)
+        if (i + 1) % B == 0 or i + 1 == st.nreq:
+            st.check_batch(i // B, acc, mism, s)
+    s.synchronize()
+    wall = time.perf_counter() - t0
+    res = {"gkeys_s": round(st.total_keys / wall / 1e9, 3), "req_s": round(st.nreq / wall, 1)}
+    if not closed_loop:
+        lat = [start.elapsed_time(evs[i]) - float(arr_s[i]) * 1e3 for i in range(st.nreq)]
+        res.update({"p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4)})
+    res.update(st.verdict(acc, mism))
+    return res
+
+
+def leg_served(binding, torch, np, inputs, pools_dev, pools_host, nreq: int, rates, rates_small,
+               alone_min_keys: int = 1 << 16):
+    """The served form against one plain launch per request, at offered rates that are fractions of
+    the plain form's measured capacity; the server with a 64 GiB budget at `rates` and with a 1 GiB
+    budget (admission binds) at `rates_small`."""
+    log(f"served: preparing {nreq} requests (input hashes, oracle sample)")
+    st = ServedTrace(binding, torch, np, inputs, pools_dev, pools_host, nreq)
+    res = {"requests": nreq, "keys_per_sweep_point": st.total_keys, "pool_keys": st.pool_keys,
+           "sample_requests": int(st.sample.size), "alone_min_keys": alone_min_keys,
+           "checks": "every output: no descent and SplitMix64 sum/xor equal to its input's (on the device); "
+                     "a seeded 1% sample of requests: keys and splitters bit-exact against the oracle"}
+    cap = run_plain(st, None, closed_loop=True)
+    plain_cap = cap["req_s"]
+    res["plain_fifo_closed_loop"] = cap
+    log(f"served: plain capacity {cap}")
+    res["points"] = []
+    with binding.Server(hbm_budget_bytes=64 << 30, num_streams=4, max_batch=256, alone_min_keys=alone_min_keys) as srv:
+        for frac in rates:
+            arr = st.arrivals(frac * plain_cap)
+            served = run_served(st, srv, arr)
+            plain = run_plain(st, arr)
+            res["points"].append({"offered_frac_of_plain_capacity": frac, "offered_req_s": round(frac * plain_cap, 1),
+                                  "served": served, "plain_fifo": plain})
+            log(f"served frac={frac}: {res['points'][-1]}")
+    res["budget_1GiB"] = []
+    with binding.Server(hbm_budget_bytes=1 << 30, num_streams=4, max_batch=256, alone_min_keys=alone_min_keys) as srv:
+        for frac in rates_small:
+            served = run_served(st, srv, st.arrivals(frac * plain_cap))
+            res["budget_1GiB"].append({"offered_frac_of_plain_capacity": frac, "served": served})
+            log(f"served 1 GiB budget frac={frac}: {served}")
+    bad = sum(p["served"]["outputs_bad"] + p["plain_fifo"]["outputs_bad"] + p["served"]["sample_keys_bad"]
+              + p["served"]["sample_splitters_bad"] for p in res["points"])
+    bad += sum(p["served"]["outputs_bad"] + p["served"]["sample_keys_bad"] + p["served"]["sample_splitters_bad"]
+               for p in res["budget_1GiB"])
+    res["all_outputs_ok"] = bad == 0
+    del st
+    return res
+
+
+# ------------------------------------------------------------------------------------------------
 def host_description() -> dict:
     """nproc, the threads this process may use, and the CPU model of the host."""
     model = None
@@ -368,11 +607,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip every extra leg")
-    ap.add_argument("--no-dists", action="store_true", help="skip distributions (b)-(e) and the 2^27 set")
+    ap.add_argument("--no-dists", action="store_true", help="skip distributions (b)-(e) and the 2^27 sets")
     ap.add_argument("--no-segmented", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=20000)
-    ap.add_argument("--served-rates", default="0.5,0.9,1.25,2.0")
+    ap.add_argument("--served-requests", type=int, default=100_000)
+    ap.add_argument("--served-rates", default="0.25,0.5,0.75,0.9,1.0,1.25,2.0",
+                    help="offered rates (fractions of the plain form's capacity), 64 GiB server budget")
+    ap.add_argument("--served-rates-1g", default="0.5,1.0,1.25,2.0",
+                    help="offered rates with a 1 GiB server budget (admission binds)")
     ap.add_argument("--alone-min-keys", type=int, default=1 << 16,
                     help="served form: requests with at least this many keys run the device-wide sort alone")
     ap.add_argument("--profile-leg", choices=["segmented", "latency", "merge"], default=None,
@@ -430,14 +672,12 @@ def main() -> int:
     ms_per_step = dt * 1e3 / args.steps
     value = N_MAIN * args.steps / dt / 1e9
     # per-kernel durations: the same sorts again with HIP events around every launch
-    _, (ms, launches) = time_sorts(binding, torch, t_in, t_out, spl, args.steps, 1, True)
-
-    pass_ms = sum(ms[binding.AP_KIND_PASS + d] for d in range(4))
-    pass_launches = sum(launches[binding.AP_KIND_PASS + d] for d in range(4))
-    pass_avg_s = pass_ms / pass_launches / 1e3
+    _, prof = time_sorts(binding, torch, t_in, t_out, spl, args.steps, 1, True)
+    ms, launches = prof
+    pass_avg_s = pass_stats(binding, prof)
     alg_bytes = 8 * N_MAIN                      # one pass reads and writes every key once
     achieved = alg_bytes / pass_avg_s / 1e9
-    traffic = read_traffic()
+    profile = read_profile()
     per_kernel_us = {
         "k_hist_plan": ms[binding.AP_KIND_HIST] / max(launches[binding.AP_KIND_HIST], 1) * 1e3,
         "k_pass": pass_avg_s * 1e6,
@@ -459,14 +699,16 @@ def main() -> int:
     copy_gbs = 10 * 8 * N_MAIN / (ce0.elapsed_time(ce1) * 1e-3) / 1e9
     del cbuf
     pools = {"a": t_in}
+    pools_host = {"a": ks.keys}
     if not args.no_extra and not args.no_dists:
         for seed, dist in zip(range(2, 6), "bcde"):
             log(f"distribution ({dist}) seed {seed}")
-            k2 = upload(inputs.keyset(dist, N_MAIN, seed=seed).keys)
+            hk = inputs.keyset(dist, N_MAIN, seed=seed).keys
+            k2 = upload(hk)
             o2 = torch.empty_like(k2)
             d2, _ = time_sorts(binding, torch, k2, o2, spl, 10, 3, False)
             extra[f"dist_{dist}_gkeys_s"] = round(N_MAIN * 10 / d2 / 1e9, 3)
-            pools[dist] = k2
+            pools[dist], pools_host[dist] = k2, hk
             del o2
         log("adversarial 2^27")
         k3 = upload(inputs.adversarial(1 << 27, seed=0).keys)
@@ -474,6 +716,10 @@ def main() -> int:
         d3, _ = time_sorts(binding, torch, k3, o3, spl, 5, 2, False)
         extra["adversarial_2p27_gkeys_s"] = round((1 << 27) * 5 / d3 / 1e9, 3)
         del k3, o3
+        log("uniform 2^27: per-pass roofline")
+        extra["uniform_2p27"] = leg_pass_2p27(binding, torch, np, inputs, spl)
+        log("bucketing variant (MSD) vs LSD")
+        extra["msd_vs_lsd_2p26"] = leg_msd(binding, torch, np, pools, spl)
     if not args.no_extra:
         log("merge 2 x 2^25")
         extra["merge_2x2p25"] = leg_merge(binding, torch, np, inputs, t_in)
@@ -484,14 +730,18 @@ def main() -> int:
     if not args.no_extra and not args.no_segmented:
         log("segmented 4096-segment batch")
         extra["segmented_4096"] = leg_segmented(binding, torch, np, inputs, steps=5)
+        log("segmented: long segments")
+        extra["segmented_long"] = leg_segmented_long(binding, torch, np, inputs, spl)
     if not args.no_extra and not args.no_served:
         for seed, dist in zip(range(2, 6), "bcde"):
             if dist not in pools:
-                pools[dist] = upload(inputs.keyset(dist, N_MAIN, seed=seed).keys)
+                pools_host[dist] = inputs.keyset(dist, N_MAIN, seed=seed).keys
+                pools[dist] = upload(pools_host[dist])
         log("served form")
         rates = [float(x) for x in args.served_rates.split(",") if x]
-        extra["served"] = leg_served(binding, torch, np, inputs, pools, args.served_requests, rates,
-                                     args.alone_min_keys)
+        rates_small = [float(x) for x in args.served_rates_1g.split(",") if x]
+        extra["served"] = leg_served(binding, torch, np, inputs, pools, pools_host, args.served_requests, rates,
+                                     rates_small, args.alone_min_keys)
 
     cpu = None
     if not args.no_cpu:
@@ -515,8 +765,11 @@ def main() -> int:
                                "+ 63 splitters, keys resident in HBM",
                    "n": N_MAIN, "P": 64, "digit_bits": 8, "passes": 4},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_pass", "alg_bytes_per_launch": alg_bytes,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profile["traffic"] if profile else None,
+                     "kernel": "k_pass", "alg_bytes_per_launch": alg_bytes, "timer": "hip_events",
+                     "rocprof_mean_us": profile["mean_us"] if profile else None,
+                     "frac_rocprof": round(alg_bytes / profile["mean_us"] / 1e3 / HBM_PEAK_GBS, 4) if profile else None,
                      "copy_ceiling_gbs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)},
         "cpu_baseline": cpu,
         "per_kernel_us": {k: round(v, 2) for k, v in per_kernel_us.items()},

@@ -103,6 +103,24 @@ ap_status ap_sort_u32_ws(const uint32_t *d_in, uint32_t *d_out, size_t n, int P,
                          void *stream);
 
 /*
+ * ap_sort_u32_msd -- ap_sort_u32 organised as bucketing on the high-order
+ * bits followed by a local sort of every bucket (Sec. 3.2 bucketing on the
+ * top bits with 4096, then 8192 buckets, Sec. 4.7; Sec. 3.3 local radix sort
+ * per cell) instead of one least-significant-digit pass per digit.  Same
+ * arguments, results and errors as ap_sort_u32.
+ *
+ * The keys are ordered by their top 16 bits (2^16 buckets) with the two
+ * high-order device-wide digit passes, the bucket boundaries are found by
+ * binary search, and the buckets are sorted in place by the batched
+ * segmented sort (one workgroup per bucket in LDS; buckets of the
+ * long-segment size and more by device-wide passes), then the splitters are
+ * written.  Scratch: the ap_sort_u32 cache of the stream plus 256 KiB, and
+ * the segmented sort's cache of the stream.
+ */
+ap_status ap_sort_u32_msd(const uint32_t *d_in, uint32_t *d_out, size_t n, int P,
+                          uint32_t *d_splitters, void *stream);
+
+/*
  * ap_sort_u32_noalloc -- ap_sort_u32 for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, results and errors as ap_sort_u32, with
@@ -216,17 +234,32 @@ ap_status ap_digit_plan_u32(const uint32_t *d_in, size_t n, int digit_bits,
  *              overlap).  The offsets live on the device, so this check
  *              completes with the stream work rather than at the call.
  *
- * One workgroup sorts each segment: segments that fit one tile are sorted in
- * registers and LDS (one read and one write of each key); longer ones by the
- * same workgroup with a histogram sweep and one sweep per non-constant digit.
- * Segments are scheduled longest first by a persistent kernel.  No host
+ * Segments shorter than the long-segment threshold (ap_segmented_set_long_min,
+ * default 2^20 keys) are sorted by one workgroup each: segments that fit one
+ * tile in registers and LDS (one read and one write of each key); longer ones
+ * by the same workgroup with a histogram sweep and one sweep per non-constant
+ * digit; they are scheduled longest first by persistent kernels, one per
+ * length group.  Segments at or above the threshold are sorted like one
+ * array, by device-wide digit passes (bucket counts per segment, then one pass
+ * per non-constant digit with a single-pass scan over the tiles of all long
+ * segments), beside the workgroup-per-segment kernels.  No host
  * synchronisation; on a non-default stream the launch sequence is captured
  * into a hipGraph and replayed while the arguments repeat.  Scratch memory
- * (4 * n_total bytes + 4 * nseg bytes + 256) is cached per device and stream.
+ * (ap_segmented_workspace_bytes: 4 * n_total bytes + 32 bytes per segment,
+ * plus, when long segments are possible, about 1 KiB per 256 keys) is cached
+ * per device and stream.
  */
 ap_status ap_sort_u32_segmented(uint32_t *d_keys, size_t n_total,
                                 const uint32_t *d_offsets, int nseg,
                                 uint32_t *d_status, void *stream);
+
+/*
+ * ap_segmented_set_long_min / ap_segmented_get_long_min -- segments of at
+ * least long_min keys are sorted by the device-wide passes (0 = never; 1 is
+ * AP_ERR_INVALID).  Process-wide; results do not depend on it.
+ */
+ap_status ap_segmented_set_long_min(size_t long_min);
+size_t ap_segmented_get_long_min(void);
 
 /* ap_segmented_workspace_bytes -- scratch size of a segmented call. */
 size_t ap_segmented_workspace_bytes(size_t n_total, int nseg);
@@ -297,6 +330,11 @@ ap_status ap_load_tuning(const char *path);
  *   everything.  No other call on the server may run concurrently with it.
  * ap_server_submit_flags: ap_server_submit with flags; AP_SUBMIT_INJECT_FAULT
  *   (testing) makes that one request fail with AP_ERR_DEVICE without running.
+ * ap_server_submit_at: ap_server_submit_flags for a request that arrived at
+ *   arrival_ns (nanoseconds on CLOCK_MONOTONIC, as clock_gettime gives it; 0
+ *   or a time in the future = now).  The latency statistics of the request
+ *   then run from its arrival rather than from the call, so time a client
+ *   spent before it could submit is counted.
  */
 typedef struct {
     size_t hbm_budget_bytes;
@@ -324,11 +362,39 @@ ap_status ap_server_submit_flags(ap_server *s, const uint32_t *d_in,
                                  uint32_t *d_out, size_t n, int P,
                                  uint32_t *d_splitters, unsigned flags,
                                  uint64_t *ticket);
+ap_status ap_server_submit_at(ap_server *s, const uint32_t *d_in,
+                              uint32_t *d_out, size_t n, int P,
+                              uint32_t *d_splitters, unsigned flags,
+                              uint64_t arrival_ns, uint64_t *ticket);
 ap_status ap_server_wait(ap_server *s, uint64_t ticket, int64_t timeout_us);
 ap_status ap_server_poll(ap_server *s, uint64_t ticket);
 ap_status ap_server_get_stats(ap_server *s, ap_server_stats *out,
                               int reset_latencies);
 ap_status ap_server_destroy(ap_server *s);
+
+/*
+ * ap_check_u32 -- check a sort's result on the device, the way the contest
+ * program checked every result it timed (Sec. 1.1).  Adds into d_acc (three
+ * uint64_t on the device, accumulated into, so zero them first):
+ *   d_acc[0] += number of i < n-1 with d_keys[i] > d_keys[i+1] (unsigned)
+ *   d_acc[1] += sum over the keys of SplitMix64(key), mod 2^64
+ *   d_acc[2] ^= xor over the keys of SplitMix64(key)
+ * An output is accepted when d_acc[0] is 0 and (d_acc[1], d_acc[2]) equal
+ * those of its input: nondecreasing, and the same multiset of keys (the hash
+ * does not depend on the order).  Reads each key once; nothing else written.
+ */
+ap_status ap_check_u32(const uint32_t *d_keys, size_t n, uint64_t *d_acc, void *stream);
+
+/*
+ * ap_check_u32_batch -- ap_check_u32 on `count` arrays in one launch
+ * (0 <= count <= 65535): array a is d_keys[a] (a device pointer read from
+ * device memory) with d_counts[a] keys, accumulated into d_acc[3a .. 3a+2].
+ * max_n is an upper bound of the counts (it sizes the launch; a larger count
+ * is still checked completely).  d_keys, d_counts and d_acc are 8-byte
+ * aligned device arrays of count (d_acc: 3 * count) entries.
+ */
+ap_status ap_check_u32_batch(const uint32_t *const *d_keys, const uint64_t *d_counts,
+                             int count, size_t max_n, uint64_t *d_acc, void *stream);
 
 /*
  * ap_release_cache -- free the scratch memory cached for ap_sort_u32,

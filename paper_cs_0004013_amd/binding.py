@@ -38,6 +38,7 @@ SIGNATURES = [
     ("ap_workspace_init", _I, [_VP, _SZ, _VP]),
     ("ap_sort_u32_ws", _I, [_VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
     ("ap_sort_u32_noalloc", _I, [_VP, _VP, _SZ, _I, _VP, _VP]),
+    ("ap_sort_u32_msd", _I, [_VP, _VP, _SZ, _I, _VP, _VP]),
     ("ap_sort_pairs_u32", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP]),
     ("ap_sort_pairs_workspace_bytes", _SZ, [_SZ]),
     ("ap_sort_pairs_u32_ws", _I, [_VP, _VP, _VP, _VP, _SZ, _I, _VP, _VP, _SZ, _VP]),
@@ -45,10 +46,14 @@ SIGNATURES = [
     ("ap_merge_adjacent_u32", _I, [_VP, _SZ, _SZ, _VP]),
     ("ap_digit_plan_u32", _I, [_VP, _SZ, _I, _VP, _VP, _VP]),
     ("ap_release_cache", _I, []),
+    ("ap_check_u32", _I, [_VP, _SZ, _VP, _VP]),
+    ("ap_check_u32_batch", _I, [_VP, _VP, _I, _SZ, _VP, _VP]),
     ("ap_profile_enable", _I, [_I]),
     ("ap_profile_read", _I, [ctypes.POINTER(ctypes.c_double), _U64P, _I]),
     ("ap_sort_u32_segmented", _I, [_VP, _SZ, _VP, _I, _VP, _VP]),
     ("ap_segmented_workspace_bytes", _SZ, [_SZ, _I]),
+    ("ap_segmented_set_long_min", _I, [_SZ]),
+    ("ap_segmented_get_long_min", _SZ, []),
     ("ap_segmented_num_configs", _I, []),
     ("ap_segmented_num_groups", _I, []),
     ("ap_segmented_config_info", _I, [_I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -59,6 +64,7 @@ SIGNATURES = [
     ("ap_server_create", _I, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)]),
     ("ap_server_submit", _I, [_VP, _VP, _VP, _SZ, _I, _VP, _U64P]),
     ("ap_server_submit_flags", _I, [_VP, _VP, _VP, _SZ, _I, _VP, ctypes.c_uint, _U64P]),
+    ("ap_server_submit_at", _I, [_VP, _VP, _VP, _SZ, _I, _VP, ctypes.c_uint, ctypes.c_uint64, _U64P]),
     ("ap_server_wait", _I, [_VP, ctypes.c_uint64, ctypes.c_int64]),
     ("ap_server_poll", _I, [_VP, ctypes.c_uint64]),
     ("ap_server_get_stats", _I, [_VP, ctypes.POINTER(ServerStats), _I]),
@@ -147,6 +153,21 @@ def ap_sort_u32(t_in, t_out, P: int = 64, t_splitters=None, stream=None) -> None
     st = lib().ap_sort_u32(_keys_ptr(t_in, "in") if n else None, _keys_ptr(t_out, "out") if n else None, n, P,
                            spl or None, _stream(stream))
     check(st, "ap_sort_u32")
+
+
+def ap_sort_u32_msd(t_in, t_out, P: int = 64, t_splitters=None, stream=None) -> None:
+    """ap_sort_u32 as bucketing on the top 16 bits, then a local sort of every bucket."""
+    n = t_in.numel()
+    if t_out.numel() != n:
+        raise ValueError("input and output sizes differ")
+    spl = None
+    if t_splitters is not None:
+        if t_splitters.numel() < max(P - 1, 0):
+            raise ValueError("splitter tensor needs P-1 entries")
+        spl = _keys_ptr(t_splitters, "splitters")
+    st = lib().ap_sort_u32_msd(_keys_ptr(t_in, "in") if n else None, _keys_ptr(t_out, "out") if n else None, n, P,
+                               spl, _stream(stream))
+    check(st, "ap_sort_u32_msd")
 
 
 NOALLOC_MAX_KEYS = 1 << 22
@@ -258,6 +279,24 @@ def ap_digit_plan_u32(t_in, digit_bits: int, t_hist, t_plan=None, stream=None) -
     check(st, "ap_digit_plan_u32")
 
 
+def ap_check_u32(t_keys, t_acc, n: int | None = None, stream=None) -> None:
+    """Accumulate (descents, sum, xor of SplitMix64) of the first n keys into t_acc (3 int64/uint64
+    on the device)."""
+    n = t_keys.numel() if n is None else n
+    if n > t_keys.numel() or t_acc.numel() < 3 or t_acc.element_size() != 8:
+        raise ValueError("bad check arguments")
+    check(lib().ap_check_u32(_keys_ptr(t_keys, "keys") if n else None, n, t_acc.data_ptr(), _stream(stream)),
+          "ap_check_u32")
+
+
+def ap_check_u32_batch(ptrs_addr: int, counts_addr: int, count: int, max_n: int, acc_addr: int,
+                       stream=None) -> None:
+    """ap_check_u32 on `count` arrays whose device pointers and key counts are stored in device
+    memory at ptrs_addr / counts_addr (uint64 each); results into 3 * count uint64 at acc_addr."""
+    check(lib().ap_check_u32_batch(ptrs_addr, counts_addr, count, max_n, acc_addr, _stream(stream)),
+          "ap_check_u32_batch")
+
+
 AP_KIND_HIST, AP_KIND_PASS, AP_KIND_FINAL, AP_KIND_SEG, AP_KIND_MERGE, AP_NKINDS = 0, 1, 9, 10, 11, 16
 
 
@@ -284,6 +323,15 @@ def ap_sort_u32_segmented(t_keys, t_offsets, t_status=None, stream=None) -> None
                                      _keys_ptr(t_status, "status") if t_status is not None else None,
                                      _stream(stream))
     check(st, "ap_sort_u32_segmented")
+
+
+def ap_segmented_set_long_min(long_min: int) -> None:
+    """Segments of at least long_min keys are sorted by device-wide passes (0 = never)."""
+    check(lib().ap_segmented_set_long_min(long_min), "ap_segmented_set_long_min")
+
+
+def ap_segmented_get_long_min() -> int:
+    return int(lib().ap_segmented_get_long_min())
 
 
 def ap_segmented_num_configs() -> int:
@@ -352,6 +400,16 @@ class Server:
         st = lib().ap_server_submit_flags(self._h, in_ptr or None, out_ptr or None, n, P, spl_ptr or None, flags,
                                           ctypes.byref(t))
         check(st, "ap_server_submit")
+        return t.value
+
+    def submit_at_ptr(self, in_ptr: int, out_ptr: int, n: int, P: int, spl_ptr: int | None, arrival_ns: int,
+                      flags: int = 0) -> int:
+        """Submit a request that arrived at ``arrival_ns`` (time.monotonic_ns(), the clock the server
+        measures latency on); its latency is counted from then."""
+        t = ctypes.c_uint64()
+        st = lib().ap_server_submit_at(self._h, in_ptr or None, out_ptr or None, n, P, spl_ptr or None, flags,
+                                       arrival_ns, ctypes.byref(t))
+        check(st, "ap_server_submit_at")
         return t.value
 
     def try_submit_ptr(self, in_ptr: int, out_ptr: int, n: int, P: int, spl_ptr: int | None = None,

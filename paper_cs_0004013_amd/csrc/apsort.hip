@@ -227,7 +227,8 @@ static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32
 
 // ---------------------------------------------------------------- launch sequence
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl,
-                       void* ws, const Layout& L, hipStream_t s, const uint32_t* d_vin, uint32_t* d_vout) {
+                       void* ws, const Layout& L, hipStream_t s, const uint32_t* d_vin, uint32_t* d_vout,
+                       int first_digit) {
   char* w = static_cast<char*>(ws);
   uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
   uint32_t* base = reinterpret_cast<uint32_t*>(w + L.base);
@@ -255,7 +256,7 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
     hipLaunchKernelGGL((k_hist_plan<kBits, kHistThreads, hist_lcopies<kBits>()>), dim3(g), dim3(kHistThreads), 0, s,
                        d_in, nn,
                        hist, base, plan, done, reinterpret_cast<uint4*>(tctr), (uint32_t)(zero_bytes / 16),
-                       inplace, (uint32_t*)nullptr, kHistCopies);
+                       inplace, (uint32_t*)nullptr, kHistCopies, first_digit);
     prof_end(s);
     ap_status st = check_launch(s, "k_hist_plan");
     if (st != AP_OK) return st;
@@ -303,6 +304,18 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
   return AP_OK;
 }
 
+ap_status enqueue_finalize(const uint32_t* d_in, uint32_t* d_out, const uint32_t* tmp, size_t n, const uint32_t* plan,
+                           int P, uint32_t* d_spl, hipStream_t s) {
+  const size_t work = std::max<size_t>(n / 4, (size_t)P);
+  uint32_t g = (uint32_t)std::min<size_t>((work + 255 * 8) / (256 * 8), (size_t)4 * device_cus());
+  g = std::max<uint32_t>(g, 1);
+  prof_begin(AP_KIND_FINAL, s);
+  hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, d_in, d_out, tmp, (uint32_t)n, plan, (uint32_t)P,
+                     P > 1 ? d_spl : nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr, (const uint32_t*)nullptr);
+  prof_end(s);
+  return check_launch(s, "k_finalize");
+}
+
 ap_status fill_u32(uint32_t* p, uint32_t value, size_t count, hipStream_t s) {
   if (!count) return AP_OK;
   uint32_t g = (uint32_t)std::min<size_t>((count + 255) / 256, 1024);
@@ -324,7 +337,7 @@ static ap_status launch_plan_only(const uint32_t* d_in, uint32_t n, uint32_t* ct
   const uint32_t g = hist_grid(n, cus);
   hipLaunchKernelGGL((k_hist_plan<BITS, kHistThreads, hist_lcopies<BITS>()>), dim3(g), dim3(kHistThreads), 0, s,
                      d_in, n, hist, base,
-                     plan, done, (uint4*)nullptr, 0u, 0, d_hist, 4u);
+                     plan, done, (uint4*)nullptr, 0u, 0, d_hist, 4u, 0);
   ap_status st = check_launch(s, "k_hist_plan");
   if (st != AP_OK || !d_plan) return st;
   // d_plan[d] = run flag of pass d, d_plan[D] = number of passes

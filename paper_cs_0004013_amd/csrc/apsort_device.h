@@ -35,6 +35,9 @@ __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
 __device__ __forceinline__ uint32_t add_agent(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned long long ld_agent_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Number of set bits of m in lanes below the calling lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {

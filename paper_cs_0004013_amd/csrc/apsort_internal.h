@@ -49,8 +49,15 @@ ap_status seg_groups_check(const SegGroup* grp);  // the used groups partition c
 void seg_reset(hipStream_t s, SegCtl* ctl);
 // d_vout != nullptr: (key, value) pairs, the values read from d_vin and written to d_vout
 // (workspace from layout_for(n, true)).
+// first_digit > 0: only digits first_digit.. are sorted on (the bucketing variant's high-order
+// passes); the output then holds the keys ordered by those digits.
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
-                       const Layout& L, hipStream_t s, const uint32_t* d_vin = nullptr, uint32_t* d_vout = nullptr);
+                       const Layout& L, hipStream_t s, const uint32_t* d_vin = nullptr, uint32_t* d_vout = nullptr,
+                       int first_digit = 0);
+ap_status cached_workspace(size_t need, hipStream_t s, void** out);
+// k_finalize alone: copy the plan's final buffer into d_out if the plan says so, and the splitters.
+ap_status enqueue_finalize(const uint32_t* d_in, uint32_t* d_out, const uint32_t* tmp, size_t n, const uint32_t* plan,
+                           int P, uint32_t* d_spl, hipStream_t s);
 
 ap_status check_sort_args(const uint32_t* d_in, const uint32_t* d_out, size_t n, int P);
 

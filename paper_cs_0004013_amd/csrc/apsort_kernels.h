@@ -10,7 +10,8 @@
 //   k_pass        Sec. 3.2 partial sort + distribution for one digit of the LSD sort (Sec. 3.3.1):
 //                 tile-local stable ranking, a single-pass scan of per-tile bucket counts with
 //                 decoupled look-back (the per-cell-per-bucket totals that Sec. 3.2 chose not to
-//                 communicate, so placement here is exact), and a scatter staged through LDS.
+//                 communicate, so placement here is exact), and a scatter staged through LDS; the
+//                 per-tile work is pass_tile (apsort_pass_core.h).
 //   k_finalize    Sec. 1.1 output contract: copy when no pass wrote the output, and the P-1
 //                 splitters (first key of each cell, footnote to Sec. 3.4.2 for uneven counts).
 #pragma once
@@ -19,6 +20,7 @@
 #include <stdint.h>
 
 #include "apsort_device.h"
+#include "apsort_pass_core.h"
 
 namespace aps {
 
@@ -36,6 +38,7 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t coun
 //   done     workgroup-completion counter, zero on entry and on exit
 //   zero_ptr/zero_vec4  scan state of the passes (tile counters + status words), cleared here
 //   out_hist optional copy of the final counts (inspection entry point)
+//   first_digit  lowest digit the plan sorts on (0 for a full sort)
 // Inside a workgroup, with 8-bit digits and 1024 threads (1024 counters), every lane position l
 // of the wave owns a private copy of the counters as 16-bit halves: bucket B is the half B & 1 of
 // LDS word (B / 2) * 64 + l, so the 64 lanes of one atomic add always hit 64 different banks
@@ -50,7 +53,7 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
     const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restrict__ g_hist,
     uint32_t* __restrict__ g_base, uint32_t* __restrict__ plan, uint32_t* __restrict__ done,
     uint4* __restrict__ zero_ptr, uint32_t zero_vec4, int inplace, uint32_t* __restrict__ out_hist,
-    uint32_t ncopies) {
+    uint32_t ncopies, int first_digit) {
   constexpr int R = 1 << BITS;
   constexpr int D = (32 + BITS - 1) / BITS;
   constexpr int HW = D * R;
@@ -175,15 +178,17 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
     for (uint32_t j = tid; j < R; j += THREADS) g_base[d * R + j] = h[d * R + j];
   }
   if (tid == 0) {
+    // Digits below first_digit are not sorted on here (the bucketing variant leaves them to the
+    // local sorts of its buckets).
     uint32_t npass = 0;
-    for (int d = 0; d < D; ++d) npass += s_const[d] ? 0u : 1u;
+    for (int d = first_digit; d < D; ++d) npass += s_const[d] ? 0u : 1u;
     // Ping-pong so that the last pass that runs writes the output: with an odd number of passes
     // the first one writes the output, with an even number it writes the scratch buffer.  In
     // place (in == out) the first pass must not write the input, so it always writes scratch.
     const uint32_t first_dst = inplace ? (uint32_t)SEL_TMP : ((npass & 1u) ? (uint32_t)SEL_OUT : (uint32_t)SEL_TMP);
     uint32_t cur = SEL_IN;
     for (int d = 0; d < kMaxDigits; ++d) {
-      const uint32_t run = (d < D && !s_const[d]) ? 1u : 0u;
+      const uint32_t run = (d >= first_digit && d < D && !s_const[d]) ? 1u : 0u;
       plan[PL_RUN + d] = run;
       plan[PL_SRC + d] = cur;
       uint32_t nxt = cur;
@@ -198,14 +203,6 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
     st_agent(done, 0u);
   }
 }
-
-// Rank primitives for the digit pass (RANK template argument of k_pass).
-enum RankKind : int {
-  RANK_ATOMIC = 0,  // LDS add-with-return on per-wave counters; relies on the LDS servicing the
-                    // conflicting lanes of one instruction in ascending lane order (checked on the
-                    // device by k_lane_order_probe before this kind is used)
-  RANK_MATCH = 1    // per-wave LDS lane masks (OR, read, clear) + leader update; order-agnostic
-};
 
 // Checks the lane-order property RANK_ATOMIC relies on: for many address patterns (all lanes on
 // one word, few words, many words, partial exec masks), lane l must get back the number of lower
@@ -239,13 +236,9 @@ __global__ __launch_bounds__(256) void k_lane_order_probe(uint32_t* __restrict__
 }
 
 // ------------------------------------------------------------------------------------------------
-// A3-A6: one digit pass over one tile of T = WAVES*64*IPT keys.
-// Keys are taken wave-striped (key j of lane l of wave w sits at w*64*IPT + j*64 + l), which is
-// memory order in (w, j, l) order, so ranking sub-step j of every wave in order is stable.
-// Order of work in a tile: claim a tile id once every wave of the workgroup is running (a tile
-// claimed early by a workgroup whose other waves start late would hold up every later tile's
-// look-back); load; rank; publish the tile's bucket counts; tile-local scan; reorder the keys in
-// LDS; look back for the global bucket starts; write the reordered keys out.
+// A3-A6: one digit pass, one workgroup per tile (pass_tile in apsort_pass_core.h).  The tile id is
+// claimed from an atomic counter while the LDS counters are cleared, so tiles start in id order
+// and the look-back of a tile only waits on tiles that are already running.
 // ------------------------------------------------------------------------------------------------
 template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN = 4, bool KV = false>
 __global__ __launch_bounds__(WAVES * 64) void k_pass(
@@ -253,179 +246,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
     const uint32_t* __restrict__ plan, const uint32_t* __restrict__ g_base,
     uint32_t* __restrict__ status, uint32_t* __restrict__ tile_ctr, const uint32_t* vin, uint32_t* vout,
     uint32_t* vtmp) {
-  constexpr int R = 1 << BITS;
-  constexpr int THREADS = WAVES * 64;
-  constexpr int T = THREADS * IPT;
-  constexpr int BPT = (R + THREADS - 1) / THREADS;
   if (plan[PL_RUN + d] == 0u) return;
   const uint32_t ssel = plan[PL_SRC + d], dsel = plan[PL_DST + d];
-  const uint32_t* __restrict__ src = ssel == SEL_IN ? in : (ssel == SEL_OUT ? out : tmp);
-  uint32_t* __restrict__ dst = dsel == SEL_OUT ? out : tmp;
+  const uint32_t* src = ssel == SEL_IN ? in : (ssel == SEL_OUT ? out : tmp);
+  uint32_t* dst = dsel == SEL_OUT ? out : tmp;
   // values (pairs only) live in the matching buffers and move exactly as their keys
-  const uint32_t* __restrict__ vsrc = ssel == SEL_IN ? vin : (ssel == SEL_OUT ? vout : vtmp);
-  uint32_t* __restrict__ vdst = dsel == SEL_OUT ? vout : vtmp;
-  const int shift = d * BITS;
-
-  __shared__ uint32_t s_cnt[WAVES * R];  // per-wave bucket counters, then per-wave run starts
-  __shared__ uint32_t s_lbase[R + 1];    // tile-local bucket starts (+ tile size)
-  __shared__ uint32_t s_delta[R];        // global start minus tile-local start, per bucket
-  __shared__ uint32_t s_stage[T];        // keys in tile-sorted order
-  __shared__ uint32_t s_vstage[KV ? T : 1];  // their values (pairs)
-  __shared__ uint32_t s_scan[WAVES];
-  __shared__ uint32_t s_tile;
-  __shared__ uint64_t s_bins[RANK == RANK_MATCH ? WAVES * R : 1];  // per-wave bucket lane masks
-
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const uint32_t* vsrc = ssel == SEL_IN ? vin : (ssel == SEL_OUT ? vout : vtmp);
+  uint32_t* vdst = dsel == SEL_OUT ? vout : vtmp;
+  __shared__ PassSmem<BITS, WAVES, IPT, RANK, KV> sm;
   // the tile claim's round trip overlaps the clearing of the counters; one barrier covers both
-  if (tid == 0) s_tile = add_agent(tile_ctr + d, 1u);
-  for (int j = tid; j < WAVES * R; j += THREADS) s_cnt[j] = 0u;
-  if constexpr (RANK == RANK_MATCH)
-    for (int j = tid; j < WAVES * R; j += THREADS) s_bins[j] = 0ull;
+  if (threadIdx.x == 0) sm.tile = add_agent(tile_ctr + d, 1u);
+  pass_clear(sm);
   __syncthreads();
-  const uint32_t tile = s_tile;
-  const uint32_t tbase = tile * (uint32_t)T;
-
-  // ---- load: keys past n become all-ones sentinels (largest digit, last in order) ----
-  uint32_t k[IPT];
-  uint32_t val[KV ? IPT : 1];
-  const uint32_t wbase = tbase + (uint32_t)(wid * 64 * IPT + lane);
-  // Every key is read once and written once per pass, and a pass streams more bytes than the
-  // caches hold: for keys alone, loads and stores carry the non-temporal hint (3-7% faster per
-  // sort).  With values beside the keys (two streams each way) the hint made passes ~30% slower,
-  // so pairs use plain accesses.
-  if (tbase + (uint32_t)T <= n) {
-    if constexpr (KV) {
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) k[j] = src[wbase + j * 64];
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) val[j] = vsrc[wbase + j * 64];
-    } else {
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) k[j] = __builtin_nontemporal_load(&src[wbase + j * 64]);
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      const uint32_t idx = wbase + j * 64;
-      k[j] = idx < n ? src[idx] : 0xFFFFFFFFu;
-      if constexpr (KV) val[j] = idx < n ? vsrc[idx] : 0u;
-    }
-  }
-
-  // ---- A4: stable rank within the wave's keys ----
-  uint32_t r[IPT];
-  uint32_t* cnt = s_cnt + wid * R;
-  if constexpr (RANK == RANK_ATOMIC) {
-    // lane-ordered LDS atomics (rank_slot), one add of 64 for a slot of one digit
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) r[j] = rank_slot(cnt, (k[j] >> shift) & (R - 1));
-  } else {
-    // Every lane ORs its lane bit into its bucket's 64-bit word, reads the word back (the lanes of
-    // this sub-step sharing the bucket) and clears it; the lowest such lane updates the counter.
-    uint64_t* bins = s_bins + wid * R;
-    const uint64_t mybit = 1ull << lane;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      const uint32_t v = (k[j] >> shift) & (R - 1);
-      // Each step needs every lane of the wave to have finished the previous one: a wave's LDS
-      // instructions run for all its lanes before the next starts.  The wave barriers (no
-      // instruction, only a scheduling fence) state that order where lanes do not run together.
-      __hip_atomic_fetch_or(&bins[v], mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      __builtin_amdgcn_wave_barrier();
-      const uint64_t m = __hip_atomic_load(&bins[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      __builtin_amdgcn_wave_barrier();
-      __hip_atomic_store(&bins[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      const uint32_t peers = lanes_below(m);
-      const uint32_t c = cnt[v];
-      __builtin_amdgcn_wave_barrier();
-      r[j] = c + peers;
-      if (peers == 0u) cnt[v] = c + (uint32_t)__popcll(m);
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-
-  // ---- tile-local run starts (one scan over bucket-major, wave-minor counts); publish the
-  //      tile's bucket counts for the look-back of later tiles ----
-  tile_bucket_offsets<R, WAVES>(s_cnt, s_lbase, s_scan);
-  uint32_t tot[BPT];
-#pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    const int b = tid + i * THREADS;
-    tot[i] = 0u;
-    if (b < R) {
-      tot[i] = s_lbase[b + 1] - s_lbase[b];
-      if (tile == 0u) st_agent(status + b, kFlagPrefix | (g_base[b] + tot[i]));
-      else st_agent(status + (size_t)tile * R + b, kFlagAgg | tot[i]);
-    }
-  }
-
-  // ---- A5 (first half): reorder the tile in LDS; independent of the global offsets ----
-  uint32_t* cnt_w = s_cnt + wid * R;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const uint32_t v = (k[j] >> shift) & (R - 1);
-    s_stage[cnt_w[v] + r[j]] = k[j];
-    if constexpr (KV) s_vstage[cnt_w[v] + r[j]] = val[j];
-  }
-
-  // ---- A3: decoupled look-back for each bucket's global start ----
-#pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    const int b = tid + i * THREADS;
-    if (b < R) {
-      uint32_t excl;
-      if (tile == 0u) {
-        excl = g_base[b];
-      } else {
-        // Sum the published counts of the preceding tiles, newest first, until one of them has
-        // published its inclusive prefix; LB_WIN status words (one per preceding tile) are
-        // fetched per round trip.
-        excl = 0u;
-        int p = (int)tile - 1;
-        while (true) {
-          uint32_t sv[LB_WIN];
-#pragma unroll
-          for (int q = 0; q < LB_WIN; ++q) sv[q] = (p - q >= 0) ? ld_agent(status + (size_t)(p - q) * R + b) : 0u;
-          int used = 0;
-          bool done = false;
-#pragma unroll
-          for (int q = 0; q < LB_WIN; ++q) {
-            if (!done && used == q) {
-              const uint32_t f = sv[q] & kFlagMask;
-              if (f != 0u) {
-                excl += sv[q] & kValueMask;
-                ++used;
-                done = (f == kFlagPrefix);
-              }
-            }
-          }
-          if (done) break;
-          p -= used;
-          if (used == 0) __builtin_amdgcn_s_sleep(1);
-        }
-        st_agent(status + (size_t)tile * R + b, kFlagPrefix | (excl + tot[i]));
-      }
-      s_delta[b] = excl - s_lbase[b];
-    }
-  }
-  __syncthreads();
-
-  // ---- A5 (second half): coalesced scatter; runs of one bucket go to consecutive addresses ----
-  const uint32_t nvalid = (n - tbase) < (uint32_t)T ? (n - tbase) : (uint32_t)T;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const uint32_t i = (uint32_t)(j * THREADS + tid);
-    if (i < nvalid) {
-      const uint32_t key = s_stage[i];
-      const uint32_t v = (key >> shift) & (R - 1);
-      if constexpr (KV) {
-        dst[s_delta[v] + i] = key;
-        vdst[s_delta[v] + i] = s_vstage[i];
-      } else {
-        __builtin_nontemporal_store(key, &dst[s_delta[v] + i]);
-      }
-    }
-  }
+  pass_tile<BITS, WAVES, IPT, RANK, LB_WIN, KV>(sm, src, dst, vsrc, vdst, n, sm.tile, d * BITS, g_base, status);
 }
 
 // ------------------------------------------------------------------------------------------------

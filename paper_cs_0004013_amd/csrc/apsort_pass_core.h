@@ -1,0 +1,211 @@
+// One tile of one digit pass of the LSD radix sort (Sec. 3.2 partial sort + distribution for one
+// digit, Sec. 3.3.1 digit order), shared by the single-array pass (k_pass) and the device-wide pass
+// over the long segments of a batched sort (k_seg_long_pass).  Templates only.
+//
+// A tile is T = WAVES*64*IPT keys, taken wave-striped (key j of lane l of wave w sits at
+// w*64*IPT + j*64 + l), which is memory order in (w, j, l) order, so ranking sub-step j of every
+// wave in order is stable.  Order of work in a tile: load; rank; publish the tile's bucket counts;
+// tile-local scan; reorder the keys in LDS; decoupled look-back for the global bucket starts (the
+// per-cell-per-bucket totals that Sec. 3.2 chose not to communicate, so placement is exact);
+// write the reordered keys out, runs of one bucket to consecutive addresses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "apsort_device.h"
+
+namespace aps {
+
+// Rank primitives of the digit pass.
+enum RankKind : int {
+  RANK_ATOMIC = 0,  // LDS add-with-return on per-wave counters; relies on the LDS servicing the
+                    // conflicting lanes of one instruction in ascending lane order (checked on the
+                    // device by k_lane_order_probe before this kind is used)
+  RANK_MATCH = 1    // per-wave LDS lane masks (OR, read, clear) + leader update; order-agnostic
+};
+
+template <int BITS, int WAVES, int IPT, int RANK, bool KV>
+struct PassSmem {
+  static constexpr int R = 1 << BITS;
+  static constexpr int T = WAVES * 64 * IPT;
+  uint32_t cnt[WAVES * R];    // per-wave bucket counters, then per-wave run starts
+  uint32_t lbase[R + 1];      // tile-local bucket starts (+ tile size)
+  uint32_t delta[R];          // global start minus tile-local start, per bucket
+  uint32_t stage[T];          // keys in tile-sorted order
+  uint32_t vstage[KV ? T : 1];  // their values (pairs)
+  uint32_t scan[WAVES];
+  uint32_t tile;
+  uint32_t aux[3];
+  uint64_t bins[RANK == RANK_MATCH ? WAVES * R : 1];  // per-wave bucket lane masks
+};
+
+// Clears the counters of the next tile (every thread takes part; a barrier must follow).
+template <int BITS, int WAVES, int IPT, int RANK, bool KV>
+__device__ __forceinline__ void pass_clear(PassSmem<BITS, WAVES, IPT, RANK, KV>& sm) {
+  constexpr int R = 1 << BITS, THREADS = WAVES * 64;
+  for (int j = threadIdx.x; j < WAVES * R; j += THREADS) sm.cnt[j] = 0u;
+  if constexpr (RANK == RANK_MATCH)
+    for (int j = threadIdx.x; j < WAVES * R; j += THREADS) sm.bins[j] = 0ull;
+}
+
+// The tile `tile` of the array src[0..n) (keys past n are all-ones sentinels: largest digit, last
+// in order, never written) for the digit at `shift`.  g_base[v] = number of keys of the whole array
+// with a smaller digit; status = look-back words of this array's tiles (R per tile, 2-bit state +
+// 30-bit count, zero before the pass).  The counters must have been cleared (pass_clear + barrier).
+template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV>
+__device__ __forceinline__ void pass_tile(PassSmem<BITS, WAVES, IPT, RANK, KV>& sm, const uint32_t* __restrict__ src,
+                                          uint32_t* __restrict__ dst, const uint32_t* __restrict__ vsrc,
+                                          uint32_t* __restrict__ vdst, uint32_t n, uint32_t tile, int shift,
+                                          const uint32_t* __restrict__ g_base, uint32_t* __restrict__ status) {
+  constexpr int R = 1 << BITS;
+  constexpr int THREADS = WAVES * 64;
+  constexpr int T = THREADS * IPT;
+  constexpr int BPT = (R + THREADS - 1) / THREADS;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const uint32_t tbase = tile * (uint32_t)T;
+
+  // ---- load ----
+  uint32_t k[IPT];
+  uint32_t val[KV ? IPT : 1];
+  const uint32_t wbase = tbase + (uint32_t)(wid * 64 * IPT + lane);
+  // Every key is read once and written once per pass, and a pass streams more bytes than the
+  // caches hold: for keys alone, loads and stores carry the non-temporal hint (3-7% faster per
+  // sort).  With values beside the keys (two streams each way) the hint made passes ~30% slower,
+  // so pairs use plain accesses.
+  if (tbase + (uint32_t)T <= n) {
+    if constexpr (KV) {
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) k[j] = src[wbase + j * 64];
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) val[j] = vsrc[wbase + j * 64];
+    } else {
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) k[j] = __builtin_nontemporal_load(&src[wbase + j * 64]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const uint32_t idx = wbase + j * 64;
+      k[j] = idx < n ? src[idx] : 0xFFFFFFFFu;
+      if constexpr (KV) val[j] = idx < n ? vsrc[idx] : 0u;
+    }
+  }
+
+  // ---- A4: stable rank within the wave's keys ----
+  uint32_t r[IPT];
+  uint32_t* cnt = sm.cnt + wid * R;
+  if constexpr (RANK == RANK_ATOMIC) {
+    // lane-ordered LDS atomics (rank_slot), one add of 64 for a slot of one digit
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) r[j] = rank_slot(cnt, (k[j] >> shift) & (R - 1));
+  } else {
+    // Every lane ORs its lane bit into its bucket's 64-bit word, reads the word back (the lanes of
+    // this sub-step sharing the bucket) and clears it; the lowest such lane updates the counter.
+    uint64_t* bins = sm.bins + wid * R;
+    const uint64_t mybit = 1ull << lane;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const uint32_t v = (k[j] >> shift) & (R - 1);
+      // Each step needs every lane of the wave to have finished the previous one: a wave's LDS
+      // instructions run for all its lanes before the next starts.  The wave barriers (no
+      // instruction, only a scheduling fence) state that order where lanes do not run together.
+      __hip_atomic_fetch_or(&bins[v], mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __builtin_amdgcn_wave_barrier();
+      const uint64_t m = __hip_atomic_load(&bins[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __builtin_amdgcn_wave_barrier();
+      __hip_atomic_store(&bins[v], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      const uint32_t peers = lanes_below(m);
+      const uint32_t c = cnt[v];
+      __builtin_amdgcn_wave_barrier();
+      r[j] = c + peers;
+      if (peers == 0u) cnt[v] = c + (uint32_t)__popcll(m);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+
+  // ---- tile-local run starts (one scan over bucket-major, wave-minor counts); publish the
+  //      tile's bucket counts for the look-back of later tiles ----
+  tile_bucket_offsets<R, WAVES>(sm.cnt, sm.lbase, sm.scan);
+  uint32_t tot[BPT];
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int b = tid + i * THREADS;
+    tot[i] = 0u;
+    if (b < R) {
+      tot[i] = sm.lbase[b + 1] - sm.lbase[b];
+      if (tile == 0u) st_agent(status + b, kFlagPrefix | (g_base[b] + tot[i]));
+      else st_agent(status + (size_t)tile * R + b, kFlagAgg | tot[i]);
+    }
+  }
+
+  // ---- A5 (first half): reorder the tile in LDS; independent of the global offsets ----
+  uint32_t* cnt_w = sm.cnt + wid * R;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const uint32_t v = (k[j] >> shift) & (R - 1);
+    sm.stage[cnt_w[v] + r[j]] = k[j];
+    if constexpr (KV) sm.vstage[cnt_w[v] + r[j]] = val[j];
+  }
+
+  // ---- A3: decoupled look-back for each bucket's global start ----
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int b = tid + i * THREADS;
+    if (b < R) {
+      uint32_t excl;
+      if (tile == 0u) {
+        excl = g_base[b];
+      } else {
+        // Sum the published counts of the preceding tiles, newest first, until one of them has
+        // published its inclusive prefix; LB_WIN status words (one per preceding tile) are
+        // fetched per round trip.
+        excl = 0u;
+        int p = (int)tile - 1;
+        while (true) {
+          uint32_t sv[LB_WIN];
+#pragma unroll
+          for (int q = 0; q < LB_WIN; ++q) sv[q] = (p - q >= 0) ? ld_agent(status + (size_t)(p - q) * R + b) : 0u;
+          int used = 0;
+          bool done = false;
+#pragma unroll
+          for (int q = 0; q < LB_WIN; ++q) {
+            if (!done && used == q) {
+              const uint32_t f = sv[q] & kFlagMask;
+              if (f != 0u) {
+                excl += sv[q] & kValueMask;
+                ++used;
+                done = (f == kFlagPrefix);
+              }
+            }
+          }
+          if (done) break;
+          p -= used;
+          if (used == 0) __builtin_amdgcn_s_sleep(1);
+        }
+        st_agent(status + (size_t)tile * R + b, kFlagPrefix | (excl + tot[i]));
+      }
+      sm.delta[b] = excl - sm.lbase[b];
+    }
+  }
+  __syncthreads();
+
+  // ---- A5 (second half): coalesced scatter; runs of one bucket go to consecutive addresses ----
+  const uint32_t nvalid = (n - tbase) < (uint32_t)T ? (n - tbase) : (uint32_t)T;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const uint32_t i = (uint32_t)(j * THREADS + tid);
+    if (i < nvalid) {
+      const uint32_t key = sm.stage[i];
+      const uint32_t v = (key >> shift) & (R - 1);
+      if constexpr (KV) {
+        dst[sm.delta[v] + i] = key;
+        vdst[sm.delta[v] + i] = sm.vstage[i];
+      } else {
+        __builtin_nontemporal_store(key, &dst[sm.delta[v] + i]);
+      }
+    }
+  }
+}
+
+}  // namespace aps

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -11,6 +12,7 @@
 #include "apsort.h"
 #include "apsort_internal.h"
 #include "apsort_seg_kernels.h"
+#include "apsort_seg_long.h"
 
 namespace aps {
 
@@ -154,17 +156,38 @@ ap_status seg_groups_check(const SegGroup* grp) {
 }
 
 
+// Segments of at least g_long_min keys (0 = none) are sorted by the device-wide passes over one
+// flat tile space (apsort_seg_long.h); shorter ones by one workgroup each.
+static std::atomic<size_t> g_long_min{(size_t)1 << 20};
+constexpr uint32_t kLongTileMin = 16384;  // flat tile of the mask-rank shape; the atomic rank uses 32K
+
 // Workspace: [SegCtl | pad to 256][order: nseg descriptors | pad][tmp n_total u32]
+//            [long segments: descriptors | bucket counts 4x256 u32 | totals 4x256 u32]
+//            [look-back words: 4 passes x flat tiles x 256 u32]
+// Segments of long_min keys or more are disjoint, so at most n_total / long_min of them; their
+// flat tiles number at most n_total / (16K-key tile) + one partial tile each.
 struct SegLayout {
-  size_t ctl, order, tmp, total;
+  size_t ctl, order, tmp, longs, lhist, lbase, lstatus, total;
+  uint32_t nlong_max, tiles_max;
+  size_t status_pass_words;
+  uint32_t long_min;  // effective threshold (all-ones: no long path)
 };
 static size_t up256(size_t x) { return (x + 255) / 256 * 256; }
-static SegLayout seg_layout(size_t n_total, int nseg) {
+static SegLayout seg_layout(size_t n_total, int nseg, size_t long_min) {
   SegLayout L{};
+  const bool longs = long_min >= 2 && long_min <= n_total;
+  L.long_min = longs ? (uint32_t)long_min : 0xFFFFFFFFu;
+  L.nlong_max = longs ? (uint32_t)(n_total / long_min) : 0u;
+  L.tiles_max = longs ? (uint32_t)((n_total + kLongTileMin - 1) / kLongTileMin + L.nlong_max) : 0u;
+  L.status_pass_words = (size_t)L.tiles_max * 256;
   size_t off = 0;
-  L.ctl = off;   off += up256(sizeof(SegCtl));
-  L.order = off; off += up256(sizeof(SegDesc) * (size_t)std::max(nseg, 1));
-  L.tmp = off;   off += up256(sizeof(uint32_t) * std::max<size_t>(n_total, 1));
+  L.ctl = off;     off += up256(sizeof(SegCtl));
+  L.order = off;   off += up256(sizeof(SegDesc) * (size_t)std::max(nseg, 1));
+  L.tmp = off;     off += up256(sizeof(uint32_t) * std::max<size_t>(n_total, 1));
+  L.longs = off;   off += up256(sizeof(LongSeg) * L.nlong_max);
+  L.lhist = off;   off += up256(sizeof(uint32_t) * 1024 * L.nlong_max);
+  L.lbase = off;   off += up256(sizeof(uint32_t) * 1024 * L.nlong_max);
+  L.lstatus = off; off += up256(sizeof(uint32_t) * 4 * L.status_pass_words);
   L.total = off;
   return L;
 }
@@ -183,18 +206,18 @@ struct SegEntry {
   int k_nseg;
   const void* k_status;
   int k_cfg;
-  // length groups after the first run on their own streams, forked from and joined back to
-  // `stream` with events (created on first use)
-  hipStream_t aux[kSegGroups];
+  // length groups after the first, and the long segments' passes, run on streams of their own,
+  // forked from and joined back to `stream` with events (created on first use)
+  hipStream_t aux[kSegGroups + 1];
   hipEvent_t ev_fork;
-  hipEvent_t ev_join[kSegGroups];
+  hipEvent_t ev_join[kSegGroups + 1];
 };
 static std::mutex g_seg_mu;
 static std::vector<SegEntry> g_seg;
 
 static ap_status seg_fork_objects(SegEntry& c) {
   if (c.ev_fork) return AP_OK;
-  for (int g = 0; g < kSegGroups; ++g) {
+  for (int g = 0; g <= kSegGroups; ++g) {
     hipError_t e = hipStreamCreateWithFlags(&c.aux[g], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c.ev_join[g], hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "segmented sort: auxiliary stream");
@@ -203,7 +226,8 @@ static ap_status seg_fork_objects(SegEntry& c) {
   return e == hipSuccess ? AP_OK : hip_fail(e, "segmented sort: fork event");
 }
 
-static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out) {
+static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out, bool* fresh) {
+  *fresh = false;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -225,8 +249,7 @@ static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out) {
       e = hipMalloc(&c.ws, bytes);
       if (e != hipSuccess) return hip_fail(e, "hipMalloc(segmented workspace)");
       c.bytes = bytes;
-      st = fill_u32(static_cast<uint32_t*>(c.ws), 0u, up256(sizeof(SegCtl)) / 4, s);
-      if (st != AP_OK) return st;
+      *fresh = true;
     }
     *out = &c;
     return seg_fork_objects(c);
@@ -237,14 +260,18 @@ static ap_status seg_entry(hipStream_t s, size_t need, SegEntry** out) {
   e = hipMalloc(&c.ws, need);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(segmented workspace)");
   c.bytes = need;
-  st = fill_u32(static_cast<uint32_t*>(c.ws), 0u, up256(sizeof(SegCtl)) / 4, s);
-  if (st != AP_OK) {
-    (void)hipFree(c.ws);
-    return st;
-  }
   g_seg.push_back(c);
   *out = &g_seg.back();
+  *fresh = true;
   return seg_fork_objects(g_seg.back());
+}
+
+// A fresh workspace: zero the control block (offset 0 whatever the sizes; every call leaves it
+// zero again).  Everything else is written by each call before it is read: the long segments'
+// bucket counts, whose place depends on the call's sizes, are zeroed by k_seg_fill.
+static ap_status seg_zero_fresh(void* ws, const SegLayout& L, hipStream_t s) {
+  char* w = static_cast<char*>(ws);
+  return fill_u32(reinterpret_cast<uint32_t*>(w + L.ctl), 0u, up256(sizeof(SegCtl)) / 4, s);
 }
 
 // The launch sequence: classify -> fill -> persistent sort.  No host synchronisation; every grid
@@ -256,13 +283,19 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
   SegCtl* ctl = reinterpret_cast<SegCtl*>(w + L.ctl);
   SegDesc* order = reinterpret_cast<SegDesc*>(w + L.order);
   uint32_t* tmp = reinterpret_cast<uint32_t*>(w + L.tmp);
+  LongSeg* longs = reinterpret_cast<LongSeg*>(w + L.longs);
+  uint32_t* lhist = reinterpret_cast<uint32_t*>(w + L.lhist);
+  uint32_t* lbase = reinterpret_cast<uint32_t*>(w + L.lbase);
+  uint32_t* lstatus = reinterpret_cast<uint32_t*>(w + L.lstatus);
   const int cus = device_cus();
+  const bool atomic_rank = lane_order_ok();
+  const uint32_t long_tile = atomic_rank ? 32768u : kLongTileMin;
   const uint32_t g1 = (uint32_t)std::min<int>((nseg + 255) / 256 + 1, 4 * cus);
   prof_begin(AP_KIND_SEG, s);
-  hipLaunchKernelGGL(k_seg_classify, dim3(g1), dim3(256), 0, s, d_off, (uint32_t)nseg, (uint32_t)n_total, ctl,
-                     d_status);
-  hipLaunchKernelGGL(k_seg_fill, dim3(g1), dim3(256), 0, s, d_off, (uint32_t)nseg, (uint32_t)n_total, ctl, d_keys,
-                     tmp, order);
+  hipLaunchKernelGGL(k_seg_classify, dim3(g1), dim3(256), 0, s, d_off, (uint32_t)nseg, (uint32_t)n_total,
+                     L.long_min, ctl, d_status);
+  hipLaunchKernelGGL(k_seg_fill, dim3(g1), dim3(256), 0, s, d_off, (uint32_t)nseg, (uint32_t)n_total, L.long_min,
+                     long_tile, ctl, d_keys, tmp, order, longs, lhist);
   // One persistent kernel per length group.  The groups sort disjoint segments and take work from
   // counters of their own, so they run concurrently: the first group (longest segments) on `s`,
   // the others on auxiliary streams forked after k_seg_fill and joined before the reset.  A
@@ -286,6 +319,37 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
     launch_seg_cfg(grp[g].cfg, grid, aux[g], order, 0u, ~0u, grp[g].cls_lo, grp[g].cls_hi, g, ctl);
     e = hipEventRecord(ev_join[g], aux[g]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, ev_join[g], 0);
+    if (e != hipSuccess) return hip_fail(e, "segmented sort: join");
+  }
+  // Long segments: bucket counts, plans, four device-wide passes and the copy back, on a stream of
+  // their own beside the group kernels.
+  if (L.nlong_max) {
+    hipStream_t ls = aux[kSegGroups];
+    e = hipStreamWaitEvent(ls, ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(fork)");
+    const uint32_t gp = std::min<uint32_t>(L.nlong_max, (uint32_t)(4 * cus));
+    const uint32_t gc = std::min<uint32_t>(L.tiles_max, (uint32_t)(4 * cus));
+    // flat tiles of 32K keys: at most n_total / 32K + one partial tile per long segment
+    const uint32_t tiles32 = (uint32_t)((n_total + 32767) / 32768 + L.nlong_max);
+    if (atomic_rank) {
+      hipLaunchKernelGGL((k_seg_long_hist<32768>), dim3(cus), dim3(1024), 0, ls, ctl, longs, lhist, lstatus,
+                         L.status_pass_words);
+      hipLaunchKernelGGL(k_seg_long_plan, dim3(gp), dim3(256), 0, ls, ctl, longs, lhist, lbase);
+      for (int d = 0; d < 4; ++d)
+        hipLaunchKernelGGL((k_seg_long_pass<16, 32, RANK_ATOMIC>), dim3(tiles32), dim3(1024), 0, ls, ctl, longs, lbase,
+                           lstatus + (size_t)d * L.status_pass_words, d);
+      hipLaunchKernelGGL((k_seg_long_copy<32768>), dim3(gc), dim3(256), 0, ls, ctl, longs);
+    } else {
+      hipLaunchKernelGGL((k_seg_long_hist<16384>), dim3(cus), dim3(1024), 0, ls, ctl, longs, lhist, lstatus,
+                         L.status_pass_words);
+      hipLaunchKernelGGL(k_seg_long_plan, dim3(gp), dim3(256), 0, ls, ctl, longs, lhist, lbase);
+      for (int d = 0; d < 4; ++d)
+        hipLaunchKernelGGL((k_seg_long_pass<8, 32, RANK_MATCH>), dim3(L.tiles_max), dim3(512), 0, ls, ctl, longs, lbase,
+                           lstatus + (size_t)d * L.status_pass_words, d);
+      hipLaunchKernelGGL((k_seg_long_copy<16384>), dim3(gc), dim3(256), 0, ls, ctl, longs);
+    }
+    e = hipEventRecord(ev_join[kSegGroups], ls);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev_join[kSegGroups], 0);
     if (e != hipSuccess) return hip_fail(e, "segmented sort: join");
   }
   seg_reset(s, ctl);
@@ -315,11 +379,16 @@ ap_status ap_sort_u32_segmented(uint32_t* d_keys, size_t n_total, const uint32_t
     ap_status gst = seg_groups_check(grp);
     if (gst != AP_OK) return gst;
   }
-  const SegLayout L = seg_layout(n_total, nseg);
+  const SegLayout L = seg_layout(n_total, nseg, g_long_min.load());
   std::lock_guard<std::mutex> lk(g_seg_mu);
   SegEntry* ent = nullptr;
-  ap_status st = seg_entry(s, L.total, &ent);
+  bool fresh = false;
+  ap_status st = seg_entry(s, L.total, &ent, &fresh);
   if (st != AP_OK) return st;
+  if (fresh) {
+    st = seg_zero_fresh(ent->ws, L, s);
+    if (st != AP_OK) return st;
+  }
   // graph key: the group table and the rank primitive (both baked into the captured kernels)
   const int cfg = seg_groups_version() * 2 + (lane_order_ok() ? 1 : 0);
 
@@ -371,8 +440,18 @@ ap_status ap_sort_u32_segmented(uint32_t* d_keys, size_t n_total, const uint32_t
 
 size_t ap_segmented_workspace_bytes(size_t n_total, int nseg) {
   if (n_total >= AP_MAX_KEYS || nseg < 0) return 0;
-  return seg_layout(n_total, nseg).total;
+  return seg_layout(n_total, nseg, g_long_min.load()).total;
 }
+
+ap_status ap_segmented_set_long_min(size_t long_min) {
+  if (long_min == 1) return fail(AP_ERR_INVALID, "long_min must be 0 (never) or at least 2");
+  g_long_min.store(long_min);
+  std::lock_guard<std::mutex> lk(g_grp_mu);
+  ++g_groups_version;  // baked into captured graphs
+  return AP_OK;
+}
+
+size_t ap_segmented_get_long_min(void) { return g_long_min.load(); }
 
 ap_status ap_segmented_set_config(int cfg) {
   if (cfg < 0 || cfg >= kNumSegCfgs) return fail(AP_ERR_INVALID, "config index out of range");

@@ -26,9 +26,10 @@ __device__ __forceinline__ int seg_class(uint32_t len) { return 32 - __clz(len -
 
 // Pass 1: validate offsets (off[s] <= off[s+1] <= n_total for every s), count segments per length
 // class; the last workgroup turns the counts into a longest-first order of classes, or into an
-// empty order when any offset was invalid, and reports the outcome through d_status.
+// empty order when any offset was invalid, and reports the outcome through d_status.  Segments of
+// long_min keys or more are not counted: they are sorted by the device-wide passes.
 __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict__ off, uint32_t nseg,
-                                                     uint32_t n_total, SegCtl* __restrict__ ctl,
+                                                     uint32_t n_total, uint32_t long_min, SegCtl* __restrict__ ctl,
                                                      uint32_t* __restrict__ d_status) {
   __shared__ uint32_t s_cnt[kSegBuckets];
   __shared__ uint32_t s_bad;
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict
       continue;
     }
     const uint32_t len = b - a;
-    if (len >= 2) atomicAdd(&s_cnt[seg_class(len)], 1u);
+    if (len >= 2 && len < long_min) atomicAdd(&s_cnt[seg_class(len)], 1u);
   }
   __syncthreads();
   if (tid < kSegBuckets && s_cnt[tid]) add_agent(&ctl->count[tid], s_cnt[tid]);
@@ -74,16 +75,36 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict
 }
 
 // Pass 2: write a descriptor for each valid segment into its class's slots of the work order
-// (in place: src == dst == keys + offset, scratch at the same offset of tmp).
+// (in place: src == dst == keys + offset, scratch at the same offset of tmp).  A segment of
+// long_min keys or more gets a LongSeg slot and a range of flat tiles of long_tile keys instead;
+// both come from one 64-bit counter, so flat tile ranges increase with the slot.
 __global__ __launch_bounds__(256) void k_seg_fill(const uint32_t* __restrict__ off, uint32_t nseg, uint32_t n_total,
-                                                 SegCtl* __restrict__ ctl, uint32_t* keys, uint32_t* tmp,
-                                                 SegDesc* __restrict__ order) {
+                                                 uint32_t long_min, uint32_t long_tile, SegCtl* __restrict__ ctl,
+                                                 uint32_t* keys, uint32_t* tmp, SegDesc* __restrict__ order,
+                                                 LongSeg* __restrict__ longs, uint32_t* __restrict__ long_hist) {
   if (ctl->bad) return;  // invalid offsets: no work
   for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < nseg; s += gridDim.x * 256) {
     const uint32_t a = off[s], b = off[s + 1];
     if (b < a || b > n_total) continue;
     const uint32_t len = b - a;
     if (len < 2) continue;
+    if (len >= long_min) {
+      const uint32_t nt = (len + long_tile - 1) / long_tile;
+      const unsigned long long got =
+          __hip_atomic_fetch_add(&ctl->long_cursor, (1ull << 32) | nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t slot = (uint32_t)(got >> 32);
+      LongSeg& ls = longs[slot];
+      ls.keys = keys + a;
+      ls.tmp = tmp + a;
+      ls.n = len;
+      ls.first_tile = (uint32_t)got;
+      ls.ntiles = nt;
+      // The slot's bucket counts start at zero: where they sit in the workspace depends on the
+      // call's sizes, so nothing a previous call left there can be trusted.
+      uint4* h = reinterpret_cast<uint4*>(long_hist + (size_t)slot * 1024);
+      for (int i = 0; i < 256; ++i) h[i] = make_uint4(0u, 0u, 0u, 0u);
+      continue;
+    }
     const int c = seg_class(len);
     SegDesc dsc;
     dsc.src = keys + a;
@@ -364,7 +385,9 @@ __global__ void k_seg_reset(SegCtl* __restrict__ ctl) {
   if (t == 0) {
     ctl->nwork = 0u;
     ctl->bad = 0u;
+    ctl->long_cursor = 0ull;
   }
+  if (t < 4) ctl->long_ctr[t] = 0u;
 }
 
 }  // namespace aps

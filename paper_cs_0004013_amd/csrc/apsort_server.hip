@@ -211,6 +211,13 @@ ap_status ap_server_submit_flags(ap_server* s, const uint32_t* d_in, uint32_t* d
   return st == AP_OK ? st : fail(st, "ap_server_submit rejected the request (status %d)", (int)st);
 }
 
+ap_status ap_server_submit_at(ap_server* s, const uint32_t* d_in, uint32_t* d_out, size_t n, int P,
+                              uint32_t* d_splitters, unsigned flags, uint64_t arrival_ns, uint64_t* ticket) {
+  if (!s) return fail(AP_ERR_INVALID, "server is NULL");
+  const ap_status st = s->core->submit(d_in, d_out, n, P, d_splitters, flags, ticket, arrival_ns);
+  return st == AP_OK ? st : fail(st, "ap_server_submit rejected the request (status %d)", (int)st);
+}
+
 ap_status ap_server_wait(ap_server* s, uint64_t ticket, int64_t timeout_us) {
   if (!s) return fail(AP_ERR_INVALID, "server is NULL");
   return s->core->wait(ticket, timeout_us);

@@ -87,8 +87,10 @@ class Server {
   ~Server() { shutdown(); }
 
   // Non-blocking: validates, applies the budget and queue bounds, queues the request.
+  // arrival_ns: the request's arrival time on the steady clock (now_ns()), from which its latency
+  // is measured; 0 = the time of this call.
   ap_status submit(const uint32_t* in, uint32_t* out, size_t n, int P, uint32_t* spl, unsigned flags,
-                   uint64_t* ticket) {
+                   uint64_t* ticket, uint64_t arrival_ns = 0) {
     if (!ticket) return AP_ERR_INVALID;
     if (P < 1 || n >= AP_MAX_KEYS || (n && (!in || !out))) return AP_ERR_INVALID;
     if (n && in != out) {
@@ -117,7 +119,8 @@ class Server {
       return AP_ERR_QUEUE_FULL;
     }
     r->ticket = ++next_ticket_;
-    r->t_submit = now_ns();
+    const uint64_t t_now = now_ns();
+    r->t_submit = (arrival_ns && arrival_ns <= t_now) ? arrival_ns : t_now;
     tickets_[r->ticket] = r;
     pending_.push_back(r);
     stats_.submitted++;

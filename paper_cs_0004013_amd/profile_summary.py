@@ -20,7 +20,8 @@ import os
 import sqlite3
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = ",".join(os.path.join(HERE, "csrc", f) for f in ("apsort_kernels.h", "apsort_device.h"))
+KERNEL_SRC = ",".join(os.path.join(HERE, "csrc", f)
+                      for f in ("apsort_kernels.h", "apsort_pass_core.h", "apsort_device.h"))
 COPY_BYTES = 4 * (1 << 26)
 
 

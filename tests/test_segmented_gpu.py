@@ -268,3 +268,67 @@ def test_empty_batch():
     t = torch.zeros(4, dtype=torch.int32, device="cuda")
     binding.ap_sort_u32_segmented(t, torch.zeros(1, dtype=torch.int32, device="cuda"))
     torch.cuda.synchronize()
+
+
+@pytest.fixture
+def long_min():
+    """Sets the long-segment threshold for one test and restores it."""
+    from paper_cs_0004013_amd import binding
+    saved = binding.ap_segmented_get_long_min()
+    yield binding.ap_segmented_set_long_min
+    binding.ap_segmented_set_long_min(saved)
+
+
+@pytest.mark.parametrize("rank_mode", [0, 1])
+def test_long_segments_device_wide(long_min, rank_mode):
+    """A low threshold sends most segments through the device-wide passes: lengths at flat-tile
+    boundaries (16K and 32K keys +-1), constant segments (no pass runs), keys below 2^24 (three
+    passes: the copy back), full-range keys, next to short segments sorted by one workgroup."""
+    from paper_cs_0004013_amd import binding
+    long_min(5000)
+    rng = np.random.default_rng(21)
+    parts, L = [], []
+    lens = [16383, 16384, 16385, 32767, 32768, 32769, 5000, 4999, 100_003, 3 * 32768 + 7, 70_000, 9000, 12,
+            250_000, 65_536]
+    for i, n in enumerate(lens):
+        kind = i % 4
+        if kind == 0:
+            k = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+        elif kind == 1:
+            k = np.full(n, 0xDEADBEEF - i, np.uint32)
+        elif kind == 2:
+            k = rng.integers(0, 1 << 24, size=n, dtype=np.uint64).astype(np.uint32)
+        else:
+            k = inputs.dist_keys("e", n, rng)
+        parts.append(k)
+        L.append(n)
+    keys = np.concatenate(parts)
+    off = np.zeros(len(L) + 1, np.int64)
+    np.cumsum(L, out=off[1:])
+    binding.ap_set_rank_mode(rank_mode)
+    try:
+        _check(keys, off.astype(np.uint32))
+        _check(keys, off.astype(np.uint32))          # graph replay / second call reuses the plans
+    finally:
+        binding.ap_set_rank_mode(0)
+
+
+def test_long_segments_mixed_batch(long_min):
+    """4 segments of 2^24 keys (distributions a, c, d, e) and 4092 log-uniform short segments,
+    with the default threshold (2^20): the long ones go device-wide."""
+    long_min(1 << 20)
+    rng = np.random.default_rng(5)
+    short = inputs.segment_lengths(4092, seed=3, lo=64, hi=1 << 14)
+    L = np.concatenate([[1 << 24] * 4, short]).astype(np.int64)
+    L = L[rng.permutation(L.size)]
+    keys, off = _batch(L)
+    _check(keys, off)
+
+
+def test_single_segment_2pow28():
+    """One segment of 2^28 keys (dist d) in a buffer with a few keys before and after it."""
+    n = 1 << 28
+    keys = inputs.keyset("d", n + 10, seed=8).keys
+    off = np.array([3, n + 3], dtype=np.uint32)
+    got = _check(keys, off)
+    assert np.array_equal(got[:3], keys[:3]) and np.array_equal(got[-7:], keys[-7:])
