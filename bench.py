@@ -101,9 +101,8 @@ def pct(v, p):
 
 
 # ------------------------------------------------------------------------------------------------
-def leg_latency(binding, torch, np, inputs):
-    """2^20 uniform keys (seed 0), 64 cells: per-sort latency over 50 timed sorts."""
-    keys = inputs.keyset("a", 1 << 20, seed=0).keys
+def sort_latency(binding, torch, np, keys):
+    """p50/p99 latency of ap_sort_u32 (64 cells) over 50 timed sorts after 5 warm-ups."""
     t_in = torch.from_numpy(keys.view(np.int32)).to("cuda")
     t_out = torch.empty_like(t_in)
     spl = torch.empty(63, dtype=torch.int32, device="cuda")
@@ -116,8 +115,17 @@ def leg_latency(binding, torch, np, inputs):
         torch.cuda.synchronize()
         if i >= 5:
             ms.append(a.elapsed_time(b))
-    return {"n": 1 << 20, "p50_ms": round(pct(ms, 50), 4), "p99_ms": round(pct(ms, 99), 4),
-            "gkeys_s_p50": round((1 << 20) / pct(ms, 50) / 1e6, 2)}
+    n = int(keys.size)
+    return {"n": n, "p50_ms": round(pct(ms, 50), 4), "p99_ms": round(pct(ms, 99), 4),
+            "gkeys_s_p50": round(n / pct(ms, 50) / 1e6, 2)}
+
+
+def leg_latency(binding, torch, np, inputs):
+    """2^20 uniform keys (seed 0), 64 cells: per-sort latency; also 2^12 and 2^14 keys, which take
+    the one-workgroup path."""
+    res = sort_latency(binding, torch, np, inputs.keyset("a", 1 << 20, seed=0).keys)
+    res["small"] = [sort_latency(binding, torch, np, inputs.keyset("a", n, seed=0).keys) for n in (1 << 12, 1 << 14)]
+    return res
 
 
 def leg_pass_2p27(binding, torch, np, inputs, spl):

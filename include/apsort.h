@@ -71,9 +71,12 @@ typedef enum {
  *
  * Digit columns whose value is the same for every key are not sorted on (the
  * pass is an identity); this is decided on the device, with no host sync.
- * Scratch memory (about 4n bytes plus the scan state) comes from a per-device,
- * per-stream cache that grows on demand; growing synchronises `stream` first.
- * Use ap_sort_u32_ws to bring your own workspace instead.
+ * Arrays of at most 16384 keys are sorted in one launch by one workgroup in
+ * registers and LDS, with no scratch memory.  Longer ones take the
+ * device-wide passes.  Their scratch memory (about 4n bytes plus the scan state)
+ * comes from a per-device, per-stream cache that grows on demand; growing
+ * synchronises `stream` first.  Use ap_sort_u32_ws to bring your own
+ * workspace instead (it always takes the device-wide passes).
  */
 ap_status ap_sort_u32(const uint32_t *d_in, uint32_t *d_out, size_t n, int P,
                       uint32_t *d_splitters, void *stream);

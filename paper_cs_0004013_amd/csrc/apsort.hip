@@ -536,6 +536,13 @@ ap_status ap_sort_u32(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, ui
   if (st != AP_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (n == 0) return sort_with_ws(d_in, d_out, 0, P, d_splitters, nullptr, 0, s);
+  // A short array is sorted in one launch by one workgroup (unless a pass shape is forced, which
+  // pins the device-wide kernels at every size).
+  if (n <= kSmallSortMax && g_shape_override.load() < 0) {
+    st = check_lane_order(s);
+    if (st != AP_OK) return st;
+    return enqueue_small_sort(d_in, d_out, n, P, d_splitters, s);
+  }
   const Layout L = layout_for(n);
   void* ws = nullptr;
   st = cached_workspace(L.total, s, &ws);

@@ -55,6 +55,10 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
                        const Layout& L, hipStream_t s, const uint32_t* d_vin = nullptr, uint32_t* d_vout = nullptr,
                        int first_digit = 0);
 ap_status cached_workspace(size_t need, hipStream_t s, void** out);
+// Arrays of at most kSmallSortMax keys: sorted in one launch by one workgroup (apsort_seg.hip).
+constexpr uint32_t kSmallSortMax = 16384;
+ap_status enqueue_small_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl,
+                             hipStream_t s);
 // k_finalize alone: copy the plan's final buffer into d_out if the plan says so, and the splitters.
 ap_status enqueue_finalize(const uint32_t* d_in, uint32_t* d_out, const uint32_t* tmp, size_t n, const uint32_t* plan,
                            int P, uint32_t* d_spl, hipStream_t s);

@@ -258,7 +258,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   if (threadIdx.x == 0) sm.tile = add_agent(tile_ctr + d, 1u);
   pass_clear(sm);
   __syncthreads();
-  pass_tile<BITS, WAVES, IPT, RANK, LB_WIN, KV>(sm, src, dst, vsrc, vdst, n, sm.tile, d * BITS, g_base, status);
+  pass_tile<BITS, WAVES, IPT, RANK, LB_WIN, KV>(sm, src, dst, vsrc, vdst, n, sm.tile, d * BITS, g_base, status,
+                                                (int)threadIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------------

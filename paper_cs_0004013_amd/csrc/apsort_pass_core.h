@@ -53,16 +53,19 @@ __device__ __forceinline__ void pass_clear(PassSmem<BITS, WAVES, IPT, RANK, KV>&
 // in order, never written) for the digit at `shift`.  g_base[v] = number of keys of the whole array
 // with a smaller digit; status = look-back words of this array's tiles (R per tile, 2-bit state +
 // 30-bit count, zero before the pass).  The counters must have been cleared (pass_clear + barrier).
+// tid = threadIdx.x (a persistent caller passes it through an opaque copy, so that the addresses
+// derived from it are not hoisted out of its loop and kept in registers for every tile).
 template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV>
 __device__ __forceinline__ void pass_tile(PassSmem<BITS, WAVES, IPT, RANK, KV>& sm, const uint32_t* __restrict__ src,
                                           uint32_t* __restrict__ dst, const uint32_t* __restrict__ vsrc,
                                           uint32_t* __restrict__ vdst, uint32_t n, uint32_t tile, int shift,
-                                          const uint32_t* __restrict__ g_base, uint32_t* __restrict__ status) {
+                                          const uint32_t* __restrict__ g_base, uint32_t* __restrict__ status,
+                                          int tid) {
   constexpr int R = 1 << BITS;
   constexpr int THREADS = WAVES * 64;
   constexpr int T = THREADS * IPT;
   constexpr int BPT = (R + THREADS - 1) / THREADS;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int lane = tid & 63, wid = tid >> 6;
   const uint32_t tbase = tile * (uint32_t)T;
 
   // ---- load ----

@@ -111,6 +111,31 @@ int seg_workgroups(int cfg, uint32_t nwork) {
 
 int seg_tile_keys(int cfg) { return kSegCfgs[cfg].waves * 64 * kSegCfgs[cfg].ipt; }
 
+// Single-array sort of n <= kSmallSortMax keys in one launch (one workgroup, keys in registers and
+// LDS): the smallest tile that holds them.
+template <int BITS, int WAVES, int IPT>
+static void launch_small(hipStream_t s, const uint32_t* in, uint32_t* out, uint32_t n, uint32_t P, uint32_t* spl) {
+  if (lane_order_ok())
+    hipLaunchKernelGGL((k_sort_small<BITS, WAVES, IPT, seg_lcopies<BITS>(), SEG_RANK_ATOMIC>), dim3(1),
+                       dim3(WAVES * 64), 0, s, in, out, n, P, spl);
+  else
+    hipLaunchKernelGGL((k_sort_small<BITS, WAVES, IPT, seg_lcopies<BITS>(), SEG_RANK_BALLOT>), dim3(1),
+                       dim3(WAVES * 64), 0, s, in, out, n, P, spl);
+}
+
+ap_status enqueue_small_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl,
+                             hipStream_t s) {
+  if (n > kSmallSortMax) return fail(AP_ERR_INVALID, "small sort takes at most %u keys", kSmallSortMax);
+  const uint32_t nn = (uint32_t)n, PP = (uint32_t)P;
+  uint32_t* spl = P > 1 ? d_spl : nullptr;
+  prof_begin(AP_KIND_SEG, s);
+  if (n <= 2048) launch_small<8, 4, 8>(s, d_in, d_out, nn, PP, spl);
+  else if (n <= 8192) launch_small<8, 16, 8>(s, d_in, d_out, nn, PP, spl);
+  else launch_small<8, 16, 16>(s, d_in, d_out, nn, PP, spl);
+  prof_end(s);
+  return check_launch(s, "k_sort_small");
+}
+
 void seg_reset(hipStream_t s, SegCtl* ctl) { hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, s, ctl); }
 
 // Length groups: group g sorts the segments whose length class ceil(log2(length)) lies in
@@ -329,14 +354,12 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(fork)");
     const uint32_t gp = std::min<uint32_t>(L.nlong_max, (uint32_t)(4 * cus));
     const uint32_t gc = std::min<uint32_t>(L.tiles_max, (uint32_t)(4 * cus));
-    // flat tiles of 32K keys: at most n_total / 32K + one partial tile per long segment
-    const uint32_t tiles32 = (uint32_t)((n_total + 32767) / 32768 + L.nlong_max);
     if (atomic_rank) {
       hipLaunchKernelGGL((k_seg_long_hist<32768>), dim3(cus), dim3(1024), 0, ls, ctl, longs, lhist, lstatus,
                          L.status_pass_words);
       hipLaunchKernelGGL(k_seg_long_plan, dim3(gp), dim3(256), 0, ls, ctl, longs, lhist, lbase);
       for (int d = 0; d < 4; ++d)
-        hipLaunchKernelGGL((k_seg_long_pass<16, 32, RANK_ATOMIC>), dim3(tiles32), dim3(1024), 0, ls, ctl, longs, lbase,
+        hipLaunchKernelGGL((k_seg_long_pass<16, 32, RANK_ATOMIC>), dim3(cus), dim3(1024), 0, ls, ctl, longs, lbase,
                            lstatus + (size_t)d * L.status_pass_words, d);
       hipLaunchKernelGGL((k_seg_long_copy<32768>), dim3(gc), dim3(256), 0, ls, ctl, longs);
     } else {
@@ -344,7 +367,7 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
                          L.status_pass_words);
       hipLaunchKernelGGL(k_seg_long_plan, dim3(gp), dim3(256), 0, ls, ctl, longs, lhist, lbase);
       for (int d = 0; d < 4; ++d)
-        hipLaunchKernelGGL((k_seg_long_pass<8, 32, RANK_MATCH>), dim3(L.tiles_max), dim3(512), 0, ls, ctl, longs, lbase,
+        hipLaunchKernelGGL((k_seg_long_pass<8, 32, RANK_MATCH>), dim3(cus), dim3(512), 0, ls, ctl, longs, lbase,
                            lstatus + (size_t)d * L.status_pass_words, d);
       hipLaunchKernelGGL((k_seg_long_copy<16384>), dim3(gc), dim3(256), 0, ls, ctl, longs);
     }

@@ -184,6 +184,69 @@ __device__ __forceinline__ void seg_rank_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>
   __syncthreads();
 }
 
+// A segment of len <= T keys sorted by the workgroup entirely in registers and LDS: per digit a
+// rank, a constant-digit test and a reorder through LDS; one read and one write of every key
+// (src == dst allowed: every key is in registers before the first write).  Then the splitters.
+template <int BITS, int WAVES, int IPT, int LCOPIES, int RANK>
+__device__ __forceinline__ void seg_sort_one_tile(SegSmem<BITS, WAVES, IPT, LCOPIES>& sm, const SegDesc& dsc,
+                                                  uint32_t len) {
+  using SM = SegSmem<BITS, WAVES, IPT, LCOPIES>;
+  constexpr int R = SM::R, D = SM::D, T = SM::T, THREADS = WAVES * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  uint32_t k[IPT], r[IPT];
+  const uint32_t lb0 = (uint32_t)(wid * 64 * IPT + lane);
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const uint32_t idx = lb0 + j * 64;
+    k[j] = idx < len ? dsc.src[idx] : 0xFFFFFFFFu;
+  }
+  const uint32_t nsent = (uint32_t)T - len;
+#pragma unroll 1
+  for (int d = 0; d < D; ++d) {
+    const int shift = d * BITS;
+    seg_rank_tile<BITS, WAVES, IPT, LCOPIES, RANK>(sm, k, r, shift);
+    // constant digit over the segment's keys (sentinels sit in the largest bucket)
+    if (tid == 0) sm.flag[0] = 0u;
+    __syncthreads();
+    const uint32_t vmax = (0xFFFFFFFFu >> shift) & (R - 1);
+    for (int b = tid; b < R; b += THREADS)
+      if (sm.tot[b] - ((uint32_t)b == vmax ? nsent : 0u) == len) sm.flag[0] = 1u;
+    __syncthreads();
+    if (sm.flag[0]) continue;  // uniform across the workgroup
+    uint32_t* cnt = sm.u.p.cnt + wid * R;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+      const uint32_t v = (k[j] >> shift) & (R - 1);
+      sm.u.p.stage[cnt[v] + r[j]] = k[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) k[j] = sm.u.p.stage[lb0 + j * 64];
+  }
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const uint32_t idx = lb0 + j * 64;
+    if (idx < len) dsc.dst[idx] = k[j];
+  }
+  seg_splitters<THREADS>(dsc, len);
+}
+
+// The single-array sort of a short array (n <= T) in one launch: one workgroup, seg_sort_one_tile.
+template <int BITS, int WAVES, int IPT, int LCOPIES, int RANK>
+__global__ __launch_bounds__(WAVES * 64) void k_sort_small(const uint32_t* src, uint32_t* dst, uint32_t n, uint32_t P,
+                                                          uint32_t* spl) {
+  __shared__ SegSmem<BITS, WAVES, IPT, LCOPIES> sm;
+  SegDesc dsc;
+  dsc.src = src;
+  dsc.dst = dst;
+  dsc.tmp = nullptr;
+  dsc.spl = spl;
+  dsc.n = n;
+  dsc.P = P;
+  dsc.pad[0] = dsc.pad[1] = 0u;
+  seg_sort_one_tile<BITS, WAVES, IPT, LCOPIES, RANK>(sm, dsc, n);
+}
+
 // Persistent segmented sort over the descriptors order[lo..hi), longest first.  With
 // item_hi == ~0u the range is that of the length classes [cls_lo, cls_hi] in the device-built
 // work order (classes are stored longest first); otherwise it is [item_lo, item_hi).  Work items
@@ -213,43 +276,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
     const uint32_t len = dsc.n;
 
     if (len <= (uint32_t)T) {
-      // ---------------- whole segment in registers + LDS ----------------
-      uint32_t k[IPT], r[IPT];
-      const uint32_t lb0 = (uint32_t)(wid * 64 * IPT + lane);
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const uint32_t idx = lb0 + j * 64;
-        k[j] = idx < len ? dsc.src[idx] : 0xFFFFFFFFu;
-      }
-      const uint32_t nsent = (uint32_t)T - len;
-#pragma unroll 1
-      for (int d = 0; d < D; ++d) {
-        const int shift = d * BITS;
-        seg_rank_tile<BITS, WAVES, IPT, LCOPIES, RANK>(sm, k, r, shift);
-        // constant digit over the segment's keys (sentinels sit in the largest bucket)
-        if (tid == 0) sm.flag[0] = 0u;
-        __syncthreads();
-        const uint32_t vmax = (0xFFFFFFFFu >> shift) & (R - 1);
-        for (int b = tid; b < R; b += THREADS)
-          if (sm.tot[b] - ((uint32_t)b == vmax ? nsent : 0u) == len) sm.flag[0] = 1u;
-        __syncthreads();
-        if (sm.flag[0]) continue;  // uniform across the workgroup
-        uint32_t* cnt = sm.u.p.cnt + wid * R;
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-          const uint32_t v = (k[j] >> shift) & (R - 1);
-          sm.u.p.stage[cnt[v] + r[j]] = k[j];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) k[j] = sm.u.p.stage[lb0 + j * 64];
-      }
-#pragma unroll
-      for (int j = 0; j < IPT; ++j) {
-        const uint32_t idx = lb0 + j * 64;
-        if (idx < len) dsc.dst[idx] = k[j];
-      }
-      seg_splitters<THREADS>(dsc, len);
+      seg_sort_one_tile<BITS, WAVES, IPT, LCOPIES, RANK>(sm, dsc, len);
       continue;
     }
 

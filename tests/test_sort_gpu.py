@@ -299,3 +299,37 @@ def test_workspace_sort_graph_capture_replay():
         want = oracle.sort_u32(keys)
         assert np.array_equal(to_host(t_out), want), f"replay {rep}"
         assert np.array_equal(to_host(spl), oracle.splitters(want, 64)), f"replay {rep} splitters"
+
+
+@pytest.mark.parametrize("rank_mode", [0, 1])
+def test_small_arrays_one_launch(rank_mode):
+    """Arrays of at most 16384 keys take the one-workgroup path of ap_sort_u32; the same keys
+    through ap_sort_u32_ws take the device-wide passes: both equal the oracle, at every tile edge
+    of the small path, in place, and with more cells than keys."""
+    torch = torch_cuda()
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_rank_mode(rank_mode)
+    try:
+        rng = np.random.default_rng(77)
+        ws = torch.empty(binding.ap_sort_workspace_bytes(16384), dtype=torch.uint8, device="cuda")
+        binding.ap_workspace_init(ws)
+        for n in (1, 2, 3, 100, 2047, 2048, 2049, 8191, 8192, 8193, 16383, 16384):
+            for dist in ("full", "e", "c"):
+                if dist == "full":
+                    keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+                else:
+                    keys = inputs.keyset(dist, n, seed=n).keys
+                announce(f"small n={n} dist={dist} rank_mode={rank_mode}")
+                want = oracle.sort_u32(keys)
+                for P in (64, n + 1):
+                    out, spl = gpu_sort(keys, P)
+                    assert np.array_equal(out, want) and np.array_equal(spl, oracle.splitters(want, P)), (n, P)
+                out, _ = gpu_sort(keys, 5, inplace=True)
+                assert np.array_equal(out, want)
+                t_in, _ = to_dev(keys)
+                t_out = torch.empty_like(t_in)
+                binding.ap_sort_u32_ws(t_in, t_out, 1, None, ws)
+                torch.cuda.synchronize()
+                assert np.array_equal(to_host(t_out), want)
+    finally:
+        binding.ap_set_rank_mode(0)
