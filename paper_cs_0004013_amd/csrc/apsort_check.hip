@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "apsort.h"
+#include "apsort_device.h"
 #include "apsort_internal.h"
 
 namespace aps {
@@ -23,7 +24,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 
 // The workgroups of one grid row sweep k[0..n): a[0] += descents (i with k[i] > k[i+1]),
 // a[1] += sum of mix64(k[i]), a[2] ^= xor of mix64(k[i]).
-__device__ __forceinline__ void check_range(const uint32_t* __restrict__ k, size_t n, unsigned long long* a) {
+__device__ __forceinline__ void check_range(gptr<const uint32_t> k, size_t n, unsigned long long* a) {
   uint64_t sum = 0, x = 0, bad = 0;
   const size_t stride = (size_t)gridDim.x * 256;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
@@ -48,14 +49,15 @@ __device__ __forceinline__ void check_range(const uint32_t* __restrict__ k, size
 
 __global__ __launch_bounds__(256) void k_check_one(const uint32_t* __restrict__ keys, size_t n,
                                                    unsigned long long* __restrict__ acc) {
-  check_range(keys, n, acc);
+  check_range(gmem(keys), n, acc);
 }
 
 // Row blockIdx.y checks array keys[y] of counts[y] keys into acc[3y .. 3y+2].
 __global__ __launch_bounds__(256) void k_check_batch(const uint32_t* const* __restrict__ keys,
                                                      const uint64_t* __restrict__ counts,
                                                      unsigned long long* __restrict__ acc) {
-  check_range(keys[blockIdx.y], counts[blockIdx.y], acc + 3 * (size_t)blockIdx.y);
+  // the array pointer is read from memory: global view, so that the loads are not flat
+  check_range(gmem(keys[blockIdx.y]), counts[blockIdx.y], acc + 3 * (size_t)blockIdx.y);
 }
 
 static unsigned check_blocks(size_t n) {

@@ -39,6 +39,18 @@ __device__ __forceinline__ unsigned long long ld_agent_u64(const unsigned long l
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Global-memory view of a pointer.  A pointer that a kernel reads from memory (a descriptor field)
+// is generic to the compiler, which then accesses it with flat instructions.  A flat access counts
+// against the LDS wait counter as well as the vector-memory one, so every LDS wait of a rank or a
+// scatter would also wait for all global loads and stores in flight.  Pointers that are kernel
+// arguments are known to be global already.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+
 // Number of set bits of m in lanes below the calling lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

@@ -253,12 +253,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   // values (pairs only) live in the matching buffers and move exactly as their keys
   const uint32_t* vsrc = ssel == SEL_IN ? vin : (ssel == SEL_OUT ? vout : vtmp);
   uint32_t* vdst = dsel == SEL_OUT ? vout : vtmp;
-  __shared__ PassSmem<BITS, WAVES, IPT, RANK, KV> sm;
+  AP_PASS_SMEM(sm, BITS, WAVES, IPT, RANK, KV);
+  __shared__ uint32_t s_tile;
   // the tile claim's round trip overlaps the clearing of the counters; one barrier covers both
-  if (threadIdx.x == 0) sm.tile = add_agent(tile_ctr + d, 1u);
+  if (threadIdx.x == 0) s_tile = add_agent(tile_ctr + d, 1u);
   pass_clear(sm);
   __syncthreads();
-  pass_tile<BITS, WAVES, IPT, RANK, LB_WIN, KV>(sm, src, dst, vsrc, vdst, n, sm.tile, d * BITS, g_base, status,
+  pass_tile<BITS, WAVES, IPT, RANK, LB_WIN, KV>(sm, src, dst, vsrc, vdst, n, s_tile, d * BITS, g_base, status,
                                                 (int)threadIdx.x);
 }
 

@@ -25,24 +25,38 @@ enum RankKind : int {
   RANK_MATCH = 1    // per-wave LDS lane masks (OR, read, clear) + leader update; order-agnostic
 };
 
+// The LDS arrays of a digit pass.  The kernel declares them as separate __shared__ arrays and
+// passes this view: the compiler then places the 128 KiB stage first and aligns each array on its
+// own, and the pass measured 3.5% faster than with the same arrays as members of one __shared__
+// struct (same instructions, other LDS offsets).
 template <int BITS, int WAVES, int IPT, int RANK, bool KV>
 struct PassSmem {
   static constexpr int R = 1 << BITS;
   static constexpr int T = WAVES * 64 * IPT;
-  uint32_t cnt[WAVES * R];    // per-wave bucket counters, then per-wave run starts
-  uint32_t lbase[R + 1];      // tile-local bucket starts (+ tile size)
-  uint32_t delta[R];          // global start minus tile-local start, per bucket
-  uint32_t stage[T];          // keys in tile-sorted order
-  uint32_t vstage[KV ? T : 1];  // their values (pairs)
-  uint32_t scan[WAVES];
-  uint32_t tile;
-  uint32_t aux[3];
-  uint64_t bins[RANK == RANK_MATCH ? WAVES * R : 1];  // per-wave bucket lane masks
+  uint32_t* cnt;    // [WAVES * R] per-wave bucket counters, then per-wave run starts
+  uint32_t* lbase;  // [R + 1] tile-local bucket starts (+ tile size)
+  uint32_t* delta;  // [R] global start minus tile-local start, per bucket
+  uint32_t* stage;  // [T] keys in tile-sorted order
+  uint32_t* vstage; // [T] their values (pairs only)
+  uint32_t* scan;   // [WAVES]
+  uint64_t* bins;   // [WAVES * R] per-wave bucket lane masks (mask rank only)
 };
+
+// Declares the LDS arrays of a digit pass in the calling kernel and the view `name` of them.
+#define AP_PASS_SMEM(name, BITS, WAVES, IPT, RANK, KV)                                              \
+  __shared__ uint32_t name##_cnt[(WAVES) * (1 << (BITS))];                                          \
+  __shared__ uint32_t name##_lbase[(1 << (BITS)) + 1];                                              \
+  __shared__ uint32_t name##_delta[1 << (BITS)];                                                    \
+  __shared__ uint32_t name##_stage[(WAVES) * 64 * (IPT)];                                           \
+  __shared__ uint32_t name##_vstage[(KV) ? (WAVES) * 64 * (IPT) : 1];                               \
+  __shared__ uint32_t name##_scan[WAVES];                                                           \
+  __shared__ uint64_t name##_bins[(RANK) == RANK_MATCH ? (WAVES) * (1 << (BITS)) : 1];              \
+  const PassSmem<BITS, WAVES, IPT, RANK, KV> name{name##_cnt,   name##_lbase, name##_delta, name##_stage, \
+                                                  name##_vstage, name##_scan, name##_bins}
 
 // Clears the counters of the next tile (every thread takes part; a barrier must follow).
 template <int BITS, int WAVES, int IPT, int RANK, bool KV>
-__device__ __forceinline__ void pass_clear(PassSmem<BITS, WAVES, IPT, RANK, KV>& sm) {
+__device__ __forceinline__ void pass_clear(const PassSmem<BITS, WAVES, IPT, RANK, KV>& sm) {
   constexpr int R = 1 << BITS, THREADS = WAVES * 64;
   for (int j = threadIdx.x; j < WAVES * R; j += THREADS) sm.cnt[j] = 0u;
   if constexpr (RANK == RANK_MATCH)
@@ -56,7 +70,7 @@ __device__ __forceinline__ void pass_clear(PassSmem<BITS, WAVES, IPT, RANK, KV>&
 // tid = threadIdx.x (a persistent caller passes it through an opaque copy, so that the addresses
 // derived from it are not hoisted out of its loop and kept in registers for every tile).
 template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV>
-__device__ __forceinline__ void pass_tile(PassSmem<BITS, WAVES, IPT, RANK, KV>& sm, const uint32_t* __restrict__ src,
+__device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK, KV>& sm, const uint32_t* __restrict__ src,
                                           uint32_t* __restrict__ dst, const uint32_t* __restrict__ vsrc,
                                           uint32_t* __restrict__ vdst, uint32_t n, uint32_t tile, int shift,
                                           const uint32_t* __restrict__ g_base, uint32_t* __restrict__ status,
@@ -67,6 +81,9 @@ __device__ __forceinline__ void pass_tile(PassSmem<BITS, WAVES, IPT, RANK, KV>& 
   constexpr int BPT = (R + THREADS - 1) / THREADS;
   const int lane = tid & 63, wid = tid >> 6;
   const uint32_t tbase = tile * (uint32_t)T;
+  // global views: the long-segment pass reads these pointers from descriptors
+  const gptr<const uint32_t> gsrc = gmem(src), gvsrc = gmem(vsrc);
+  const gptr<uint32_t> gdst = gmem(dst), gvdst = gmem(vdst);
 
   // ---- load ----
   uint32_t k[IPT];
@@ -79,19 +96,19 @@ __device__ __forceinline__ void pass_tile(PassSmem<BITS, WAVES, IPT, RANK, KV>& 
   if (tbase + (uint32_t)T <= n) {
     if constexpr (KV) {
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) k[j] = src[wbase + j * 64];
+      for (int j = 0; j < IPT; ++j) k[j] = gsrc[wbase + j * 64];
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) val[j] = vsrc[wbase + j * 64];
+      for (int j = 0; j < IPT; ++j) val[j] = gvsrc[wbase + j * 64];
     } else {
 #pragma unroll
-      for (int j = 0; j < IPT; ++j) k[j] = __builtin_nontemporal_load(&src[wbase + j * 64]);
+      for (int j = 0; j < IPT; ++j) k[j] = __builtin_nontemporal_load(&gsrc[wbase + j * 64]);
     }
   } else {
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const uint32_t idx = wbase + j * 64;
-      k[j] = idx < n ? src[idx] : 0xFFFFFFFFu;
-      if constexpr (KV) val[j] = idx < n ? vsrc[idx] : 0u;
+      k[j] = idx < n ? gsrc[idx] : 0xFFFFFFFFu;
+      if constexpr (KV) val[j] = idx < n ? gvsrc[idx] : 0u;
     }
   }
 
@@ -202,10 +219,10 @@ __device__ __forceinline__ void pass_tile(PassSmem<BITS, WAVES, IPT, RANK, KV>& 
       const uint32_t key = sm.stage[i];
       const uint32_t v = (key >> shift) & (R - 1);
       if constexpr (KV) {
-        dst[sm.delta[v] + i] = key;
-        vdst[sm.delta[v] + i] = sm.vstage[i];
+        gdst[sm.delta[v] + i] = key;
+        gvdst[sm.delta[v] + i] = sm.vstage[i];
       } else {
-        __builtin_nontemporal_store(key, &dst[sm.delta[v] + i]);
+        __builtin_nontemporal_store(key, &gdst[sm.delta[v] + i]);
       }
     }
   }

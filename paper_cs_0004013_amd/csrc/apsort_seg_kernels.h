@@ -150,9 +150,10 @@ __device__ __forceinline__ void seg_splitters(const SegDesc& dsc, uint32_t len) 
   if (!dsc.spl) return;
   __syncthreads();
   const uint32_t P = dsc.P, q = len / P, r = len % P;
+  const gptr<uint32_t> spl = gmem(dsc.spl), out = gmem(dsc.dst);
   for (uint32_t p = threadIdx.x + 1; p < P; p += THREADS) {
     const uint64_t start = (uint64_t)p * q + (p < r ? p : r);
-    dsc.spl[p - 1] = start < len ? dsc.dst[start] : 0xFFFFFFFFu;
+    spl[p - 1] = start < len ? out[start] : 0xFFFFFFFFu;
   }
 }
 
@@ -195,10 +196,12 @@ __device__ __forceinline__ void seg_sort_one_tile(SegSmem<BITS, WAVES, IPT, LCOP
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   uint32_t k[IPT], r[IPT];
   const uint32_t lb0 = (uint32_t)(wid * 64 * IPT + lane);
+  const gptr<const uint32_t> in = gmem(dsc.src);
+  const gptr<uint32_t> out = gmem(dsc.dst);
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const uint32_t idx = lb0 + j * 64;
-    k[j] = idx < len ? dsc.src[idx] : 0xFFFFFFFFu;
+    k[j] = idx < len ? in[idx] : 0xFFFFFFFFu;
   }
   const uint32_t nsent = (uint32_t)T - len;
 #pragma unroll 1
@@ -226,7 +229,7 @@ __device__ __forceinline__ void seg_sort_one_tile(SegSmem<BITS, WAVES, IPT, LCOP
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const uint32_t idx = lb0 + j * 64;
-    if (idx < len) dsc.dst[idx] = k[j];
+    if (idx < len) out[idx] = k[j];
   }
   seg_splitters<THREADS>(dsc, len);
 }
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
     }
 
     // ---------------- longer segment: histogram sweep, then one sweep per digit ----------------
-    const uint32_t* __restrict__ seg = dsc.src;
+    const gptr<const uint32_t> seg = gmem(dsc.src);
     for (int i = tid; i < LCOPIES * CS; i += THREADS) sm.u.hist[i] = 0u;
     __syncthreads();
     {
@@ -293,18 +296,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
       uint32_t head = (uint32_t)(((16u - ((uintptr_t)seg & 15u)) & 15u) >> 2);
       if (head > len) head = len;
       if ((uint32_t)tid < head) count(seg[tid]);
-      const uint4* __restrict__ v4 = reinterpret_cast<const uint4*>(seg + head);
+      // 16-byte loads through a clang vector type (HIP's uint4 class has no copy from a global
+      // reference)
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      const gptr<const u32x4> v4 = reinterpret_cast<gptr<const u32x4>>(seg + head);
       const uint32_t nv = (len - head) >> 2;
       uint32_t i = tid;
       for (; i + 3 * THREADS < nv; i += 4 * THREADS) {
-        const uint4 x0 = v4[i], x1 = v4[i + THREADS], x2 = v4[i + 2 * THREADS], x3 = v4[i + 3 * THREADS];
+        const u32x4 x0 = v4[i], x1 = v4[i + THREADS], x2 = v4[i + 2 * THREADS], x3 = v4[i + 3 * THREADS];
         count(x0.x); count(x0.y); count(x0.z); count(x0.w);
         count(x1.x); count(x1.y); count(x1.z); count(x1.w);
         count(x2.x); count(x2.y); count(x2.z); count(x2.w);
         count(x3.x); count(x3.y); count(x3.z); count(x3.w);
       }
       for (; i < nv; i += THREADS) {
-        const uint4 x = v4[i];
+        const u32x4 x = v4[i];
         count(x.x); count(x.y); count(x.z); count(x.w);
       }
       for (uint32_t j = head + nv * 4 + tid; j < len; j += THREADS) count(seg[j]);
@@ -327,9 +333,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
     uint32_t npass = 0;
     for (int d = 0; d < D; ++d) npass += sm.flag[d] ? 0u : 1u;
     const bool inplace = dsc.src == dsc.dst;
-    const uint32_t* src = seg;
-    uint32_t* dst = (inplace || !(npass & 1u)) ? dsc.tmp : dsc.dst;
-    uint32_t* other = (dst == dsc.tmp) ? dsc.dst : dsc.tmp;
+    const gptr<uint32_t> g_dst = gmem(dsc.dst), g_tmp = gmem(dsc.tmp);
+    gptr<const uint32_t> src = seg;
+    gptr<uint32_t> dst = (inplace || !(npass & 1u)) ? g_tmp : g_dst;
+    gptr<uint32_t> other = (dst == g_tmp) ? g_dst : g_tmp;
     const uint32_t ntile = (len + T - 1) / T;
     const uint32_t lb0 = (uint32_t)(wid * 64 * IPT + lane);
 #pragma unroll 1
@@ -379,13 +386,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_sort(const SegDesc* __restri
         for (int b = tid; b < R; b += THREADS) sm.running[b] += sm.tot[b];
       }
       src = dst;
-      uint32_t* nxt = other;
+      gptr<uint32_t> nxt = other;
       other = dst;
       dst = nxt;
       __syncthreads();  // this sweep's writes are complete before the next sweep reads them
     }
-    if (src != dsc.dst) {  // no sweep ran (copy) or, in place, an odd number ended in tmp
-      for (uint32_t i = tid; i < len; i += THREADS) dsc.dst[i] = src[i];
+    if (src != g_dst) {  // no sweep ran (copy) or, in place, an odd number ended in tmp
+      for (uint32_t i = tid; i < len; i += THREADS) g_dst[i] = src[i];
     }
     __syncthreads();
     seg_splitters<THREADS>(dsc, len);

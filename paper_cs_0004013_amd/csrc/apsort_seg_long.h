@@ -29,6 +29,17 @@ __device__ __forceinline__ uint32_t long_slot(const LongSeg* __restrict__ longs,
   }
   return lo;
 }
+// The same search over the first tiles cached in LDS.
+__device__ __forceinline__ uint32_t long_slot_lds(const uint32_t* first, uint32_t nlong, uint32_t f) {
+  uint32_t lo = 0, hi = nlong;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (first[mid] <= f) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+constexpr uint32_t kLongSlotCache = 512;  // first tiles of up to this many long segments kept in LDS
 
 // Bucket counts of every 8-bit digit of every long segment, and zeroed look-back words for every
 // flat tile.  Workgroup w takes a contiguous range of flat tiles (tiles of one segment are mostly
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_seg_long_hist(const SegCtl* __restrict
     const uint32_t last = min(min(f1, seg_end), f + kLongHistFlush);
     const uint32_t k0 = (f - ls.first_tile) * (uint32_t)TILE;
     const uint32_t k1 = min(ls.n, (last - ls.first_tile) * (uint32_t)TILE);
-    const uint32_t* __restrict__ keys = ls.keys;
+    const gptr<const uint32_t> keys = gmem(ls.keys);
     uint32_t i = k0 + tid;
     for (; i + 3u * 1024u < k1; i += 4u * 1024u) {
       const uint32_t a0 = keys[i], a1 = keys[i + 1024u], a2 = keys[i + 2048u], a3 = keys[i + 3072u];
@@ -152,20 +163,27 @@ template <int WAVES, int IPT, int RANK>
 __global__ __launch_bounds__(WAVES * 64) void k_seg_long_pass(SegCtl* __restrict__ ctl, const LongSeg* __restrict__ longs,
                                                              const uint32_t* __restrict__ base,
                                                              uint32_t* __restrict__ status, int d) {
-  __shared__ PassSmem<8, WAVES, IPT, RANK, false> sm;
+  AP_PASS_SMEM(sm, 8, WAVES, IPT, RANK, false);
+  __shared__ uint32_t s_tile, s_slot;
+  __shared__ uint32_t s_first[kLongSlotCache];
   const unsigned long long cur = ld_agent_u64(&ctl->long_cursor);
   const uint32_t nlong = (uint32_t)(cur >> 32), ntiles = (uint32_t)cur;
   if (ntiles == 0u) return;
+  // the segments' first tiles in LDS: a tile's segment is then found without global round trips
+  // (the first barrier of the loop orders these writes before any search)
+  const bool cached = nlong <= kLongSlotCache;
+  if (cached)
+    for (uint32_t s = threadIdx.x; s < nlong; s += WAVES * 64) s_first[s] = longs[s].first_tile;
 #pragma unroll 1
   while (true) {
     if (threadIdx.x == 0) {
       const uint32_t f = add_agent(&ctl->long_ctr[d], 1u);
-      sm.tile = f;
-      sm.aux[0] = f < ntiles ? long_slot(longs, nlong, f) : 0u;
+      s_tile = f;
+      s_slot = f >= ntiles ? 0u : cached ? long_slot_lds(s_first, nlong, f) : long_slot(longs, nlong, f);
     }
     pass_clear(sm);
     __syncthreads();
-    const uint32_t f = sm.tile, slot = sm.aux[0];
+    const uint32_t f = s_tile, slot = s_slot;
     if (f >= ntiles) break;
     const LongSeg& ls = longs[slot];
     if (ls.run[d]) {
@@ -193,7 +211,8 @@ __global__ __launch_bounds__(256) void k_seg_long_copy(const SegCtl* __restrict_
     if (!ls.final_tmp) continue;
     const uint32_t k0 = (f - ls.first_tile) * (uint32_t)TILE;
     const uint32_t k1 = min(ls.n, k0 + (uint32_t)TILE);
-    for (uint32_t i = k0 + threadIdx.x; i < k1; i += 256) ls.keys[i] = ls.tmp[i];
+    const gptr<uint32_t> keys = gmem(ls.keys), tmp = gmem(ls.tmp);
+    for (uint32_t i = k0 + threadIdx.x; i < k1; i += 256) keys[i] = tmp[i];
   }
 }
 
