@@ -224,16 +224,25 @@ def check_arrays(binding, torch, np, base_ptr: int, offsets, stream=None):
     """Device check of the arrays [offsets[s], offsets[s+1]) of the int32 buffer at base_ptr:
     (descents, SplitMix64 sum, xor) per array, as a (nseg, 3) uint64 numpy array."""
     off = np.asarray(offsets, dtype=np.int64)
-    nseg = off.size - 1
-    ptrs = torch.from_numpy(base_ptr + 4 * off[:-1]).to("cuda")
-    cnts = torch.from_numpy(np.diff(off)).to("cuda")
-    acc = torch.zeros((nseg, 3), dtype=torch.int64, device="cuda")
-    for s0 in range(0, nseg, 4096):
-        c = min(4096, nseg - s0)
-        binding.ap_check_u32_batch(ptrs.data_ptr() + 8 * s0, cnts.data_ptr() + 8 * s0, c, int(np.diff(off).max()),
-                                   acc.data_ptr() + 24 * s0, stream)
-    torch.cuda.synchronize()
-    return acc.cpu().numpy().view(np.uint64)
+    lens = np.diff(off)
+    out = np.zeros((lens.size, 3), dtype=np.uint64)
+    # A batched check launches (arrays x blocks for its longest array) workgroups: arrays of more
+    # than 2^20 keys are checked one per call, the rest in batches sized by the longest of them.
+    big = lens > (1 << 20)
+    for sel in (np.nonzero(big)[0], np.nonzero(~big)[0]):
+        if sel.size == 0:
+            continue
+        ptrs = torch.from_numpy(base_ptr + 4 * off[sel]).to("cuda")
+        cnts = torch.from_numpy(lens[sel]).to("cuda")
+        acc = torch.zeros((sel.size, 3), dtype=torch.int64, device="cuda")
+        step = 1 if big[sel[0]] else 4096
+        for s0 in range(0, sel.size, step):
+            c = min(step, sel.size - s0)
+            binding.ap_check_u32_batch(ptrs.data_ptr() + 8 * s0, cnts.data_ptr() + 8 * s0, c,
+                                       int(lens[sel[s0:s0 + c]].max()), acc.data_ptr() + 24 * s0, stream)
+        torch.cuda.synchronize()
+        out[sel] = acc.cpu().numpy().view(np.uint64)
+    return out
 
 
 def leg_segmented(binding, torch, np, inputs, steps: int, baseline: bool = True):
@@ -625,7 +634,7 @@ def main() -> int:
                     help="offered rates with a 1 GiB server budget (admission binds)")
     ap.add_argument("--alone-min-keys", type=int, default=1 << 16,
                     help="served form: requests with at least this many keys run the device-wide sort alone")
-    ap.add_argument("--profile-leg", choices=["segmented", "latency", "merge"], default=None,
+    ap.add_argument("--profile-leg", choices=["segmented", "segmented-long", "latency", "merge"], default=None,
                     help="run only that leg (for rocprofv3) and print its result")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration under rocprofv3)")
@@ -657,6 +666,10 @@ def main() -> int:
     binding.lib()
     if args.profile_leg == "segmented":
         print(json.dumps(leg_segmented(binding, torch, np, inputs, steps=3, baseline=False)), flush=True)
+        return 0
+    if args.profile_leg == "segmented-long":
+        spl = torch.empty(63, dtype=torch.int32, device="cuda")
+        print(json.dumps(leg_segmented_long(binding, torch, np, inputs, spl, steps=3)), flush=True)
         return 0
     if args.profile_leg == "latency":
         print(json.dumps(leg_latency(binding, torch, np, inputs)), flush=True)

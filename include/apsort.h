@@ -394,7 +394,10 @@ ap_status ap_check_u32(const uint32_t *d_keys, size_t n, uint64_t *d_acc, void *
  * device memory) with d_counts[a] keys, accumulated into d_acc[3a .. 3a+2].
  * max_n is an upper bound of the counts (it sizes the launch; a larger count
  * is still checked completely).  d_keys, d_counts and d_acc are 8-byte
- * aligned device arrays of count (d_acc: 3 * count) entries.
+ * aligned device arrays of count (d_acc: 3 * count) entries.  The launch has
+ * count rows of min(ceil(max_n / 4096), 4 x CUs) workgroups, so batch arrays
+ * of similar lengths: one 2^24-key array among 4095 short ones makes
+ * 4096 x 1024 workgroups, most of which find no work (~20 ms).
  */
 ap_status ap_check_u32_batch(const uint32_t *const *d_keys, const uint64_t *d_counts,
                              int count, size_t max_n, uint64_t *d_acc, void *stream);
