@@ -634,7 +634,7 @@ def main() -> int:
                     help="offered rates with a 1 GiB server budget (admission binds)")
     ap.add_argument("--alone-min-keys", type=int, default=1 << 16,
                     help="served form: requests with at least this many keys run the device-wide sort alone")
-    ap.add_argument("--profile-leg", choices=["segmented", "segmented-long", "latency", "merge"], default=None,
+    ap.add_argument("--profile-leg", choices=["segmented", "segmented-long", "msd", "latency", "merge"], default=None,
                     help="run only that leg (for rocprofv3) and print its result")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration under rocprofv3)")
@@ -670,6 +670,19 @@ def main() -> int:
     if args.profile_leg == "segmented-long":
         spl = torch.empty(63, dtype=torch.int32, device="cuda")
         print(json.dumps(leg_segmented_long(binding, torch, np, inputs, spl, steps=3)), flush=True)
+        return 0
+    if args.profile_leg == "msd":
+        # the bucketing variant alone (three sorts of 2^26 keys each of (a) and (e)), for its counters
+        spl = torch.empty(63, dtype=torch.int32, device="cuda")
+        res = {}
+        for dist in ("a", "e"):
+            t_in = torch.from_numpy(inputs.keyset(dist, N_MAIN, seed=1).keys.view(np.int32)).to("cuda")
+            out = torch.empty_like(t_in)
+            for _ in range(3):
+                binding.ap_sort_u32_msd(t_in, out, 64, spl)
+            torch.cuda.synchronize()
+            res[dist] = bool(torch.equal(out, torch.sort(t_in)[0]))
+        print(json.dumps({"msd_sorted": res}), flush=True)
         return 0
     if args.profile_leg == "latency":
         print(json.dumps(leg_latency(binding, torch, np, inputs)), flush=True)

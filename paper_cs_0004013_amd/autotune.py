@@ -30,7 +30,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tune_gfx950.txt")
 GROUPS = [(14, 31), (13, 13), (12, 12), (1, 11)]   # > 8K, (4K, 8K], (2K, 4K], <= 2K keys
-START = [10, 1, 5, 3]                               # configurations the descent starts from (the built-in table)
+START = [10, 0, 5, 3]                               # configurations the descent starts from (the built-in table)
 TUNE_SEEDS = (7919, 104729, 1299709)
 
 

@@ -146,7 +146,7 @@ void seg_reset(hipStream_t s, SegCtl* ctl) { hipLaunchKernelGGL(k_seg_reset, dim
 // rewrites the table (ap_segmented_set_group, ap_load_tuning).
 static std::mutex g_grp_mu;
 // length classes ceil(log2(len)): one group per tile size (16K keys, also taking longer segments; 8K; 4K; 2K)
-static SegGroup g_groups[kSegGroups] = {{14, 31, 10}, {13, 13, 1}, {12, 12, 5}, {1, 11, 3}, {1, 0, 0}, {1, 0, 0}};
+static SegGroup g_groups[kSegGroups] = {{14, 31, 10}, {13, 13, 0}, {12, 12, 5}, {1, 11, 3}, {1, 0, 0}, {1, 0, 0}};
 static int g_groups_version = 0;  // bumped on every change (invalidates captured graphs)
 
 int seg_groups_version() {
