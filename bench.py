@@ -356,6 +356,49 @@ def leg_segmented_long(binding, torch, np, inputs, spl, steps: int = 5):
 
 
 # ------------------------------------------------------------------------------------------------
+def phase_trace(binding, torch, np, inputs, sorts: int = 5) -> str:
+    """Per-tile phase timestamps of the digit passes of a 2^26 uniform sort (the traced kernel,
+    ap_debug_pass mode 2, which adds two barriers and a wait for its stores), as a markdown
+    summary: duration of each phase per tile, and the mean number of tiles in flight."""
+    n = N_MAIN
+    t_in = torch.from_numpy(inputs.keyset("a", n, seed=1).keys.view(np.int32)).to("cuda")
+    t_out = torch.empty_like(t_in)
+    tile = 16 * 64 * 32
+    ntiles = (n + tile - 1) // tile
+    W = binding.PASS_TRACE_WORDS
+    trace = torch.zeros(4 * ntiles * W, dtype=torch.int64, device="cuda")
+    binding.ap_debug_pass(binding.PASS_DBG_TRACE, 0, trace)
+    try:
+        for _ in range(sorts):
+            binding.ap_sort_u32(t_in, t_out, 64, None)
+        torch.cuda.synchronize()
+    finally:
+        binding.ap_debug_pass(binding.PASS_DBG_NONE)
+    ok = bool(torch.equal(t_out, torch.sort(t_in)[0]))
+    rec = trace.cpu().numpy().reshape(4, ntiles, W)[:, :, :6].astype(np.float64) / 100.0  # 100 MHz -> us
+    names = ["claim to rank done (loads + rank)", "scan of the tile's counts", "publish + LDS reorder",
+             "look-back", "scatter (stores complete)"]
+    lines = ["# k_pass phase timestamps, 2^26 uniform 31-bit keys (dist a, seed 1), 32K-key tiles", "",
+             "Command (run from the repository root on an MI355X):", "", "```",
+             "python3 bench.py --phase-trace > profiles/k_pass_phases_uniform_2p26.md", "```", "",
+             f"The last of {sorts} sorts; traced kernel (ap_debug_pass mode 2: per-tile s_memrealtime stamps by "
+             "thread 0, with a barrier after the rank and after the reorder and a wait for the scatter's stores). "
+             f"Output sorted: {ok}.", "",
+             "| phase | mean us | p50 us | p90 us |", "|---|---|---|---|"]
+    for i, nm in enumerate(names):
+        dur = (rec[:, :, i + 1] - rec[:, :, i]).ravel()
+        lines.append(f"| {nm} | {dur.mean():.2f} | {np.percentile(dur, 50):.2f} | {np.percentile(dur, 90):.2f} |")
+    tot = (rec[:, :, 5] - rec[:, :, 0]).ravel()
+    lines.append(f"| whole tile | {tot.mean():.2f} | {np.percentile(tot, 50):.2f} | {np.percentile(tot, 90):.2f} |")
+    lines += ["", "| pass | wall us (first claim to last scatter) | mean tiles in flight |", "|---|---|---|"]
+    for d in range(4):
+        wall = rec[d, :, 5].max() - rec[d, :, 0].min()
+        busy = (rec[d, :, 5] - rec[d, :, 0]).sum()
+        lines.append(f"| {d} | {wall:.1f} | {busy / wall:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
+# ------------------------------------------------------------------------------------------------
 class ServedTrace:
     """The served workload: nreq requests, request r drawing its size (log-uniform [2^10, 2^24]),
     distribution and window into that distribution's device-resident pool from seed r.  Sizes,
@@ -636,6 +679,8 @@ def main() -> int:
                     help="served form: requests with at least this many keys run the device-wide sort alone")
     ap.add_argument("--profile-leg", choices=["segmented", "segmented-long", "msd", "latency", "merge"], default=None,
                     help="run only that leg (for rocprofv3) and print its result")
+    ap.add_argument("--phase-trace", action="store_true",
+                    help="print per-phase tile durations of k_pass at 2^26 (ap_debug_pass trace mode) as markdown")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -664,6 +709,9 @@ def main() -> int:
                           "launches": 5}), flush=True)
         return 0
     binding.lib()
+    if args.phase_trace:
+        print(phase_trace(binding, torch, np, inputs), flush=True)
+        return 0
     if args.profile_leg == "segmented":
         print(json.dumps(leg_segmented(binding, torch, np, inputs, steps=3, baseline=False)), flush=True)
         return 0

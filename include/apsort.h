@@ -445,6 +445,31 @@ int ap_rank_check_state(void);
 ap_status ap_set_rank_mode(int mode);
 
 /*
+ * ap_debug_pass -- debug mode of the device-wide digit pass (Sec. 3.2 partial
+ * sort and distribution of one digit), process-wide, for the keys-only passes
+ * of ap_sort_u32, ap_sort_u32_ws, ap_sort_u32_noalloc and ap_sort_u32_msd.
+ * The passes then run a separate kernel; the default kernels are not changed.
+ *   mode 0: off (default).
+ *   mode 1: timing perturbation.  Every tile sleeps, with probability 1/2 per
+ *     point and for 0 - 12 us drawn from SplitMix64(seed, tile, digit, point),
+ *     after its claim, before its scan, before its reorder, before the
+ *     look-back, before publishing its inclusive prefix and before its scatter.
+ *     Tiles then publish and finish in orders the normal timing seldom gives:
+ *     a stress test of the look-back.  Results are unchanged (bit for bit).
+ *   mode 2: phase trace.  d_trace (device memory, 8-byte aligned, holding
+ *     trace_records records of 8 uint64) receives, for tile t of pass d of the
+ *     last sort (record d * tiles + t; records beyond trace_records are not
+ *     written), the wall clock (s_memrealtime, 100 MHz) when the tile was
+ *     claimed, ranked, scanned, reordered, looked back and scattered (stores
+ *     complete); words 6 and 7 are not written.  The trace kernel adds
+ *     barriers after the rank and the reorder and waits for its stores, so a
+ *     traced pass runs slightly slower.  d_trace must stay valid while sorts
+ *     run in this mode.
+ * Errors: AP_ERR_INVALID (mode outside 0..2; mode 2 without a buffer).
+ */
+ap_status ap_debug_pass(int mode, uint64_t seed, unsigned long long *d_trace, size_t trace_records);
+
+/*
  * Tile shape of the device-wide digit pass (Sec. 3.2 partial sort and
  * distribution, one digit of the LSD sort of Sec. 3.3.1).  By default the
  * tile grows with the array: 2K keys below 2^19, 4K below 2^22, 16K below

@@ -72,6 +72,7 @@ SIGNATURES = [
     ("ap_rank_check_state", _I, []),
     ("ap_set_rank_mode", _I, [_I]),
     ("ap_set_pass_shape", _I, [_I]),
+    ("ap_debug_pass", _I, [_I, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t]),
     ("ap_last_error", ctypes.c_char_p, []),
     ("ap_version", ctypes.c_char_p, []),
 ]
@@ -462,6 +463,19 @@ def ap_rank_check_state() -> int:
 def ap_set_rank_mode(mode: int) -> None:
     """0 = automatic (atomic rank when the device passed its lane-order check), 1 = mask rank."""
     check(lib().ap_set_rank_mode(mode), "ap_set_rank_mode")
+
+
+PASS_DBG_NONE, PASS_DBG_PERTURB, PASS_DBG_TRACE = 0, 1, 2
+PASS_TRACE_WORDS = 8
+
+
+def ap_debug_pass(mode: int, seed: int = 0, t_trace=None) -> None:
+    """Debug mode of the keys-only digit pass: 0 off, 1 seeded timing perturbation, 2 phase trace
+    into t_trace (an int64 device tensor of 8 words per record)."""
+    ptr, recs = None, 0
+    if t_trace is not None:
+        ptr, recs = t_trace.data_ptr(), t_trace.numel() // PASS_TRACE_WORDS
+    check(lib().ap_debug_pass(mode, seed, ptr, recs), "ap_debug_pass")
 
 
 def ap_set_pass_shape(shape: int = -1) -> None:

@@ -225,6 +225,49 @@ static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32
                      base_d, st_d, tctr, vin, vout, vtmp);
 }
 
+// Debug mode of the digit pass (ap_debug_pass): the keys-only passes then run k_pass_dbg.
+struct PassDebugState {
+  int mode;
+  uint64_t seed;
+  unsigned long long* trace;
+  uint64_t trace_records;
+};
+static std::mutex g_dbg_mu;
+static PassDebugState g_dbg{PASS_DBG_NONE, 0, nullptr, 0};
+static PassDebugState pass_debug() {
+  std::lock_guard<std::mutex> lk(g_dbg_mu);
+  return g_dbg;
+}
+
+template <int W, int I, int DBG>
+static void launch_pass_dbg_mode(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out,
+                                 uint32_t* tmp, uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d,
+                                 uint32_t* st_d, uint32_t* tctr, const PassDebugArgs& a) {
+  if constexpr (W * 64 * I <= 16384) {
+    if (!atomic_rank) {
+      hipLaunchKernelGGL((k_pass_dbg<kBits, W, I, RANK_MATCH, DBG>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d,
+                         plan, base_d, st_d, tctr, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_pass_dbg<kBits, W, I, RANK_ATOMIC, DBG>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d, plan,
+                     base_d, st_d, tctr, a);
+}
+template <int W, int I>
+static void launch_pass_dbg(const PassDebugState& st, bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in,
+                            uint32_t* out, uint32_t* tmp, uint32_t n, int d, uint32_t ntiles, const uint32_t* plan,
+                            const uint32_t* base_d, uint32_t* st_d, uint32_t* tctr) {
+  PassDebugArgs a{};
+  a.seed = st.seed;
+  a.trace = st.trace;
+  a.trace_records = st.trace_records;
+  a.record0 = (uint32_t)d * ntiles;
+  if (st.mode == PASS_DBG_PERTURB)
+    launch_pass_dbg_mode<W, I, PASS_DBG_PERTURB>(atomic_rank, grid, s, in, out, tmp, n, d, plan, base_d, st_d, tctr, a);
+  else
+    launch_pass_dbg_mode<W, I, PASS_DBG_TRACE>(atomic_rank, grid, s, in, out, tmp, n, d, plan, base_d, st_d, tctr, a);
+}
+
 // ---------------------------------------------------------------- launch sequence
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl,
                        void* ws, const Layout& L, hipStream_t s, const uint32_t* d_vin, uint32_t* d_vout,
@@ -262,14 +305,17 @@ ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, u
     if (st != AP_OK) return st;
   }
   // A3-A6: one launch per digit; passes the plan skips exit at once
+  const PassDebugState dbg = pass_debug();
   for (int d = 0; d < kDigits; ++d) {
     uint32_t* st_d = status + (size_t)d * ntiles * kRadix;
     const uint32_t* base_d = base + d * kRadix;
     prof_begin(AP_KIND_PASS + d, s);
     const dim3 grid(ntiles);
-#define APS_PASS(W, I, KV)                                                                                    \
-  launch_pass<W, I, KV>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr, d_vin, d_vout, \
-                        vtmp)
+#define APS_PASS(W, I, KV)                                                                                      \
+  if (!KV && dbg.mode != PASS_DBG_NONE)                                                                          \
+    launch_pass_dbg<W, I>(dbg, atomic_rank, grid, s, d_in, d_out, tmp, nn, d, ntiles, plan, base_d, st_d, tctr); \
+  else                                                                                                           \
+    launch_pass<W, I, KV>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr, d_vin, d_vout, vtmp)
     if (pairs) {
       switch (sh) {
         case 2: APS_PASS(8, 32, true); break;
@@ -532,6 +578,7 @@ ap_status ap_workspace_init(void* d_ws, size_t ws_bytes, void* stream) {
 
 ap_status ap_sort_u32(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_splitters,
                       void* stream) {
+  ApRange range("ap_sort_u32");
   ap_status st = check_sort_args(d_in, d_out, n, P);
   if (st != AP_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -552,6 +599,7 @@ ap_status ap_sort_u32(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, ui
 
 ap_status ap_sort_u32_ws(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_splitters,
                          void* d_ws, size_t ws_bytes, void* stream) {
+  ApRange range("ap_sort_u32_ws");
   ap_status st = check_sort_args(d_in, d_out, n, P);
   if (st != AP_OK) return st;
   return sort_with_ws(d_in, d_out, n, P, d_splitters, d_ws, ws_bytes, static_cast<hipStream_t>(stream));
@@ -564,6 +612,7 @@ size_t ap_sort_pairs_workspace_bytes(size_t n) {
 
 ap_status ap_sort_pairs_u32(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_t* d_keys_out,
                             uint32_t* d_vals_out, size_t n, int P, uint32_t* d_splitters, void* stream) {
+  ApRange range("ap_sort_pairs_u32");
   ap_status st = check_pairs_args(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, P);
   if (st != AP_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -578,6 +627,7 @@ ap_status ap_sort_pairs_u32(const uint32_t* d_keys_in, const uint32_t* d_vals_in
 ap_status ap_sort_pairs_u32_ws(const uint32_t* d_keys_in, const uint32_t* d_vals_in, uint32_t* d_keys_out,
                                uint32_t* d_vals_out, size_t n, int P, uint32_t* d_splitters, void* d_ws,
                                size_t ws_bytes, void* stream) {
+  ApRange range("ap_sort_pairs_u32_ws");
   ap_status st = check_pairs_args(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, P);
   if (st != AP_OK) return st;
   return pairs_with_ws(d_keys_in, d_vals_in, d_keys_out, d_vals_out, n, P, d_splitters, d_ws, ws_bytes,
@@ -586,6 +636,7 @@ ap_status ap_sort_pairs_u32_ws(const uint32_t* d_keys_in, const uint32_t* d_vals
 
 ap_status ap_digit_plan_u32(const uint32_t* d_in, size_t n, int digit_bits, uint32_t* d_hist, uint32_t* d_plan,
                             void* stream) {
+  ApRange range("ap_digit_plan_u32");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (digit_bits < 4 || digit_bits > 11) return fail(AP_ERR_INVALID, "digit_bits must be in [4, 11]");
   if (n >= AP_MAX_KEYS) return fail(AP_ERR_INVALID, "n must be < 2^30");
@@ -601,6 +652,17 @@ int ap_rank_check_state(void) { return lane_order_state(); }
 ap_status ap_set_rank_mode(int mode) {
   if (mode != 0 && mode != 1) return fail(AP_ERR_INVALID, "rank mode must be 0 (auto) or 1 (match)");
   set_rank_mode(mode);
+  return AP_OK;
+}
+
+ap_status ap_debug_pass(int mode, uint64_t seed, unsigned long long* d_trace, size_t trace_records) {
+  if (mode < PASS_DBG_NONE || mode > PASS_DBG_TRACE) return fail(AP_ERR_INVALID, "debug mode must be 0, 1 or 2");
+  if (mode == PASS_DBG_TRACE && (!d_trace || trace_records == 0))
+    return fail(AP_ERR_INVALID, "the trace mode needs a trace buffer");
+  if (((uintptr_t)d_trace) & 7u) return fail(AP_ERR_INVALID, "trace buffer must be 8-byte aligned");
+  std::lock_guard<std::mutex> lk(g_dbg_mu);
+  g_dbg = PassDebugState{mode, seed, mode == PASS_DBG_TRACE ? d_trace : nullptr,
+                         mode == PASS_DBG_TRACE ? (uint64_t)trace_records : 0u};
   return AP_OK;
 }
 

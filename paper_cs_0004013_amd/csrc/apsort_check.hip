@@ -72,6 +72,7 @@ using namespace aps;
 extern "C" {
 
 ap_status ap_check_u32(const uint32_t* d_keys, size_t n, uint64_t* d_acc, void* stream) {
+  ApRange range("ap_check_u32");
   if (!d_acc || ((uintptr_t)d_acc & 7u)) return fail(AP_ERR_INVALID, "d_acc must be an 8-byte aligned device pointer");
   if (n && (!d_keys || ((uintptr_t)d_keys & 3u))) return fail(AP_ERR_INVALID, "bad key pointer");
   if (n == 0) return AP_OK;
@@ -83,6 +84,7 @@ ap_status ap_check_u32(const uint32_t* d_keys, size_t n, uint64_t* d_acc, void* 
 
 ap_status ap_check_u32_batch(const uint32_t* const* d_keys, const uint64_t* d_counts, int count, size_t max_n,
                              uint64_t* d_acc, void* stream) {
+  ApRange range("ap_check_u32_batch");
   if (count < 0 || count > 65535) return fail(AP_ERR_INVALID, "count must be in [0, 65535]");
   if (count == 0) return AP_OK;
   if (!d_keys || !d_counts || !d_acc || (((uintptr_t)d_keys | (uintptr_t)d_counts | (uintptr_t)d_acc) & 7u))

@@ -5,9 +5,20 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "apsort.h"
 
 namespace aps {
+
+// A roctx range around a library call (named after the entry point), seen by a tracer such as
+// rocprofv3 --marker-trace; without a tracer attached the push and pop return at once.
+struct ApRange {
+  explicit ApRange(const char* name) { roctxRangePushA(name); }
+  ~ApRange() { roctxRangePop(); }
+  ApRange(const ApRange&) = delete;
+  ApRange& operator=(const ApRange&) = delete;
+};
 
 // Byte offsets of the single-array sort workspace (see layout_for).
 struct Layout {

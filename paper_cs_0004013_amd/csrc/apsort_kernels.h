@@ -263,6 +263,29 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
                                                 (int)threadIdx.x);
 }
 
+// k_pass (keys only) with a debug mode of pass_tile (PassDebug): seeded timing perturbation, or
+// per-tile phase timestamps.  Launched instead of k_pass only while ap_debug_pass is set.
+template <int BITS, int WAVES, int IPT, int RANK, int DBG>
+__global__ __launch_bounds__(WAVES * 64) void k_pass_dbg(
+    const uint32_t* in, uint32_t* out, uint32_t* tmp, uint32_t n, int d, const uint32_t* __restrict__ plan,
+    const uint32_t* __restrict__ g_base, uint32_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
+    PassDebugArgs dbg) {
+  if (plan[PL_RUN + d] == 0u) return;
+  const uint32_t ssel = plan[PL_SRC + d], dsel = plan[PL_DST + d];
+  const uint32_t* src = ssel == SEL_IN ? in : (ssel == SEL_OUT ? out : tmp);
+  uint32_t* dst = dsel == SEL_OUT ? out : tmp;
+  AP_PASS_SMEM(sm, BITS, WAVES, IPT, RANK, false);
+  __shared__ uint32_t s_tile;
+  if (threadIdx.x == 0) s_tile = add_agent(tile_ctr + d, 1u);
+  pass_clear(sm);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if constexpr (DBG == PASS_DBG_TRACE) dbg_stamp(dbg, tile, 0);
+  if constexpr (DBG == PASS_DBG_PERTURB) dbg_delay(dbg, tile, d * BITS, 0);
+  pass_tile<BITS, WAVES, IPT, RANK, 4, false, DBG>(sm, src, dst, nullptr, nullptr, n, tile, d * BITS, g_base, status,
+                                                   (int)threadIdx.x, &dbg);
+}
+
 // ------------------------------------------------------------------------------------------------
 // A7: output contract.  Copies the sorted keys into the output when no pass wrote it, and writes
 // splitter p-1 = first key of cell p (all-ones for an empty cell).

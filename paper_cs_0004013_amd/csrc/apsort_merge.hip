@@ -251,6 +251,7 @@ extern "C" {
 
 ap_status ap_merge_u32(const uint32_t* d_a, size_t na, const uint32_t* d_b, size_t nb, uint32_t* d_out,
                        void* stream) {
+  ApRange range("ap_merge_u32");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (na >= AP_MAX_KEYS || nb >= AP_MAX_KEYS || na + nb >= AP_MAX_KEYS)
     return fail(AP_ERR_INVALID, "na + nb must be < 2^30");
@@ -267,6 +268,7 @@ ap_status ap_merge_u32(const uint32_t* d_a, size_t na, const uint32_t* d_b, size
 }
 
 ap_status ap_merge_adjacent_u32(uint32_t* d_keys, size_t na, size_t nb, void* stream) {
+  ApRange range("ap_merge_adjacent_u32");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (na >= AP_MAX_KEYS || nb >= AP_MAX_KEYS || na + nb >= AP_MAX_KEYS)
     return fail(AP_ERR_INVALID, "na + nb must be < 2^30");

@@ -51,6 +51,7 @@ extern "C" {
 
 ap_status ap_sort_u32_noalloc(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_splitters,
                               void* stream) {
+  ApRange range("ap_sort_u32_noalloc");
   ap_status st = check_sort_args(d_in, d_out, n, P);
   if (st != AP_OK) return st;
   if (n > AP_NOALLOC_MAX_KEYS)

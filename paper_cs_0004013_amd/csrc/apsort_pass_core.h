@@ -63,18 +63,56 @@ __device__ __forceinline__ void pass_clear(const PassSmem<BITS, WAVES, IPT, RANK
     for (int j = threadIdx.x; j < WAVES * R; j += THREADS) sm.bins[j] = 0ull;
 }
 
+// Debug modes of the digit pass, compiled only into the k_pass_dbg instantiations (the default
+// kernels carry none of this code).
+//   PASS_DBG_PERTURB: seeded delays of up to ~10 us at the tile claim and before the aggregate,
+//     the reorder, the inclusive prefix and the scatter, so that tiles publish and finish in an
+//     order the normal timing seldom produces (a stress of the look-back and the claim order).
+//   PASS_DBG_TRACE: wall-clock timestamps (s_memrealtime, 100 MHz) at the tile's phase boundaries,
+//     written by thread 0 as kPassTraceWords words per tile at trace[(pass * ntiles + tile) * 8];
+//     the trace build adds a barrier after the rank and after the reorder, and waits for the
+//     scatter's stores, so that each phase ends for the whole workgroup at its timestamp.
+enum PassDebug : int { PASS_DBG_NONE = 0, PASS_DBG_PERTURB = 1, PASS_DBG_TRACE = 2 };
+constexpr int kPassTraceWords = 8;  // claim, rank, scan, reorder, look-back, scatter, 2 spare
+struct PassDebugArgs {
+  uint64_t seed;                    // perturbation seed
+  unsigned long long* trace;        // trace records (NULL: none)
+  uint64_t trace_records;           // capacity in records of kPassTraceWords words
+  uint32_t record0;                 // record index of tile 0 of this pass (pass * ntiles)
+  uint32_t pad;
+};
+
+__device__ __forceinline__ uint64_t dbg_mix(uint64_t z) {  // SplitMix64 finaliser
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// A seeded delay, the same for every thread of the workgroup: no delay on half of the draws,
+// otherwise up to three sleeps of 8128 cycles plus up to 4032 (about 0 - 12 us at 2.4 GHz).
+__device__ __forceinline__ void dbg_delay(const PassDebugArgs& dbg, uint32_t tile, int shift, int point) {
+  const uint64_t h = dbg_mix(dbg.seed ^ ((uint64_t)tile << 16) ^ ((uint64_t)shift << 8) ^ (uint64_t)point);
+  if (h & 1u) return;
+  for (uint32_t i = 0; i < (uint32_t)((h >> 1) & 3u); ++i) __builtin_amdgcn_s_sleep(127);
+  for (uint32_t i = 0; i < (uint32_t)((h >> 3) & 63u); ++i) __builtin_amdgcn_s_sleep(1);
+}
+__device__ __forceinline__ void dbg_stamp(const PassDebugArgs& dbg, uint32_t tile, int word) {
+  if (threadIdx.x == 0 && dbg.trace && (uint64_t)dbg.record0 + tile < dbg.trace_records)
+    dbg.trace[((uint64_t)dbg.record0 + tile) * kPassTraceWords + word] = __builtin_amdgcn_s_memrealtime();
+}
+
 // The tile `tile` of the array src[0..n) (keys past n are all-ones sentinels: largest digit, last
 // in order, never written) for the digit at `shift`.  g_base[v] = number of keys of the whole array
 // with a smaller digit; status = look-back words of this array's tiles (R per tile, 2-bit state +
 // 30-bit count, zero before the pass).  The counters must have been cleared (pass_clear + barrier).
 // tid = threadIdx.x (a persistent caller passes it through an opaque copy, so that the addresses
 // derived from it are not hoisted out of its loop and kept in registers for every tile).
-template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV>
+template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV, int DBG = PASS_DBG_NONE>
 __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK, KV>& sm, const uint32_t* __restrict__ src,
                                           uint32_t* __restrict__ dst, const uint32_t* __restrict__ vsrc,
                                           uint32_t* __restrict__ vdst, uint32_t n, uint32_t tile, int shift,
                                           const uint32_t* __restrict__ g_base, uint32_t* __restrict__ status,
-                                          int tid) {
+                                          int tid, const PassDebugArgs* dbg = nullptr) {
   constexpr int R = 1 << BITS;
   constexpr int THREADS = WAVES * 64;
   constexpr int T = THREADS * IPT;
@@ -146,7 +184,13 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
 
   // ---- tile-local run starts (one scan over bucket-major, wave-minor counts); publish the
   //      tile's bucket counts for the look-back of later tiles ----
+  if constexpr (DBG == PASS_DBG_TRACE) {
+    __syncthreads();
+    dbg_stamp(*dbg, tile, 1);
+  }
+  if constexpr (DBG == PASS_DBG_PERTURB) dbg_delay(*dbg, tile, shift, 1);
   tile_bucket_offsets<R, WAVES>(sm.cnt, sm.lbase, sm.scan);
+  if constexpr (DBG == PASS_DBG_TRACE) dbg_stamp(*dbg, tile, 2);
   uint32_t tot[BPT];
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
@@ -159,6 +203,7 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
     }
   }
 
+  if constexpr (DBG == PASS_DBG_PERTURB) dbg_delay(*dbg, tile, shift, 2);
   // ---- A5 (first half): reorder the tile in LDS; independent of the global offsets ----
   uint32_t* cnt_w = sm.cnt + wid * R;
 #pragma unroll
@@ -168,6 +213,11 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
     if constexpr (KV) sm.vstage[cnt_w[v] + r[j]] = val[j];
   }
 
+  if constexpr (DBG == PASS_DBG_TRACE) {
+    __syncthreads();
+    dbg_stamp(*dbg, tile, 3);
+  }
+  if constexpr (DBG == PASS_DBG_PERTURB) dbg_delay(*dbg, tile, shift, 3);
   // ---- A3: decoupled look-back for each bucket's global start ----
 #pragma unroll
   for (int i = 0; i < BPT; ++i) {
@@ -203,12 +253,15 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
           p -= used;
           if (used == 0) __builtin_amdgcn_s_sleep(1);
         }
+        if constexpr (DBG == PASS_DBG_PERTURB) dbg_delay(*dbg, tile, shift, 4);
         st_agent(status + (size_t)tile * R + b, kFlagPrefix | (excl + tot[i]));
       }
       sm.delta[b] = excl - sm.lbase[b];
     }
   }
   __syncthreads();
+  if constexpr (DBG == PASS_DBG_TRACE) dbg_stamp(*dbg, tile, 4);
+  if constexpr (DBG == PASS_DBG_PERTURB) dbg_delay(*dbg, tile, shift, 5);
 
   // ---- A5 (second half): coalesced scatter; runs of one bucket go to consecutive addresses ----
   const uint32_t nvalid = (n - tbase) < (uint32_t)T ? (n - tbase) : (uint32_t)T;
@@ -225,6 +278,11 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
         __builtin_nontemporal_store(key, &gdst[sm.delta[v] + i]);
       }
     }
+  }
+  if constexpr (DBG == PASS_DBG_TRACE) {
+    __builtin_amdgcn_s_waitcnt(0);  // every counter zero: this thread's stores have completed
+    __syncthreads();
+    dbg_stamp(*dbg, tile, 5);
   }
 }
 

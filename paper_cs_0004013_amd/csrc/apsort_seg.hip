@@ -389,6 +389,7 @@ extern "C" {
 
 ap_status ap_sort_u32_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_offsets, int nseg,
                                 uint32_t* d_status, void* stream) {
+  ApRange range("ap_sort_u32_segmented");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (nseg < 0) return fail(AP_ERR_INVALID, "nseg must be >= 0");
   if (n_total >= AP_MAX_KEYS) return fail(AP_ERR_INVALID, "n_total must be < 2^30");

@@ -84,6 +84,7 @@ class HipExecutor : public srv::Executor {
   void thread_init() override { (void)hipSetDevice(dev_); }
 
   ap_status launch_batch(int slot, std::vector<srv::Request*>& reqs) override {
+    ApRange range("ap_server batch");
     SlotRes& sl = slots_[slot];
     std::sort(reqs.begin(), reqs.end(), [](const srv::Request* a, const srv::Request* b) { return a->n > b->n; });
     size_t used = 0;

@@ -76,3 +76,14 @@ def test_invalid_arguments_rejected_on_host():
     assert L.ap_merge_u32(None, 10, 8192, 10, 65536, None) == 1            # NULL run
     assert L.ap_merge_adjacent_u32(4096, 1 << 29, 1 << 29, None) == 1      # na + nb >= 2^30
     assert L.ap_merge_adjacent_u32(4098, 10, 10, None) == 1                # misaligned
+
+
+def test_debug_pass_arguments():
+    L = binding.lib()
+    assert L.ap_debug_pass(3, 0, None, 0) == 1           # mode outside 0..2
+    assert L.ap_debug_pass(-1, 0, None, 0) == 1
+    assert L.ap_debug_pass(2, 0, None, 0) == 1           # trace mode without a buffer
+    assert L.ap_debug_pass(2, 0, 4096, 0) == 1           # ... or without records
+    assert L.ap_debug_pass(2, 0, 4100, 16) == 1          # misaligned buffer
+    assert L.ap_debug_pass(1, 7, None, 0) == 0           # perturbation on, then off again
+    assert L.ap_debug_pass(0, 0, None, 0) == 0
