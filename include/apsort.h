@@ -309,8 +309,14 @@ ap_status ap_load_tuning(const char *path);
  * batch formed on a slot that frees up.  The caller keeps every buffer alive
  * until its ticket completes.
  *
- *   hbm_budget_bytes  scratch memory of the server (split evenly over the
- *                     slots and allocated at creation); default 64 GiB.
+ *   hbm_budget_bytes  scratch memory of the server: one arena allocated at
+ *                     creation and shared by all slots; default 64 GiB.  It is
+ *                     kept as a ledger: a batch or a long request reserves the
+ *                     byte range it needs (first fit) when it is launched and
+ *                     returns it when it completes, so a long request may use
+ *                     nearly all of it.  A long request at the queue head that
+ *                     does not fit yet waits, and meanwhile only requests that
+ *                     need no scratch (at most 2048 keys) are launched.
  *   num_streams       slots = concurrent batches; default 4.
  *   max_batch         requests per batch; default 256.
  *   max_queue         queued requests before AP_ERR_QUEUE_FULL; default 65536.
@@ -320,15 +326,17 @@ ap_status ap_load_tuning(const char *path);
  * Zero fields take the default.
  *
  * ap_server_submit: AP_ERR_INVALID for bad arguments, AP_ERR_BUDGET when the
- *   request can never fit one slot's scratch, AP_ERR_QUEUE_FULL when the queue
- *   is full.  Nothing is queued then.
+ *   request's scratch exceeds the whole budget (it could never run),
+ *   AP_ERR_QUEUE_FULL when the queue is full.  Nothing is queued then.
  * ap_server_wait: the ticket's final status (AP_OK, AP_ERR_DEVICE when its
  *   device work failed, AP_ERR_CANCELLED when the server was destroyed before
  *   it ran), or AP_ERR_TIMEOUT after timeout_us microseconds (< 0: no limit).
  *   A ticket whose final status has been returned is forgotten.
  * ap_server_poll: like ap_server_wait with a zero timeout.
- * ap_server_get_stats: counters and submit-to-completion latency percentiles
- *   of the completed requests (since creation or the last reset).
+ * ap_server_get_stats: counters, submit-to-completion latency and
+ *   submit-to-launch queueing percentiles of the completed requests (since
+ *   creation or the last reset), and the scratch arena's size and peak use
+ *   (since creation).
  * ap_server_destroy: cancels queued requests, waits for running ones, frees
  *   everything.  No other call on the server may run concurrently with it.
  * ap_server_submit_flags: ap_server_submit with flags; AP_SUBMIT_INJECT_FAULT
@@ -351,6 +359,9 @@ typedef struct {
     uint64_t submitted, completed, failed, cancelled, batches, alone, keys;
     uint64_t latency_samples;
     double p50_us, p99_us, mean_us, max_us;
+    double queue_p50_us, queue_p99_us;  /* submit (or arrival) to launch */
+    uint64_t scratch_budget_bytes;      /* size of the shared scratch arena */
+    uint64_t scratch_peak_bytes;        /* most scratch reserved at once */
 } ap_server_stats;
 
 typedef struct ap_server ap_server;

@@ -27,7 +27,9 @@ class ServerCfg(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "completed", "failed", "cancelled", "batches", "alone",
                                               "keys", "latency_samples")] + \
-               [(f, ctypes.c_double) for f in ("p50_us", "p99_us", "mean_us", "max_us")]
+               [(f, ctypes.c_double) for f in ("p50_us", "p99_us", "mean_us", "max_us", "queue_p50_us",
+                                              "queue_p99_us")] + \
+               [(f, ctypes.c_uint64) for f in ("scratch_budget_bytes", "scratch_peak_bytes")]
 
 
 # (name, restype, argtypes) of every exported entry point

@@ -1,14 +1,16 @@
 // HIP executor and C entry points of the sort-request server (ap_server_*).
 //
-// Each slot owns a non-blocking stream, a completion event and a scratch arena carved from the
-// memory budget: [segmented-sort control block][descriptor array][scratch].  A batch of short
-// requests becomes one launch of the persistent segmented kernel over host-built descriptors
-// (longest first), each descriptor pointing at the caller's input and output buffers directly, so
-// no key is copied in or out.  A long request runs alone through the device-wide sort with the
-// arena as its workspace.
+// Each slot owns a non-blocking stream, a completion event and a small header on the device (the
+// segmented-sort control block and the descriptor array).  Scratch comes from one arena of the
+// memory budget, shared by the slots through the core's ledger.  A batch of short requests
+// becomes one launch of the persistent segmented kernel over host-built descriptors (longest
+// first), each descriptor pointing at the caller's input and output buffers directly, so no key is
+// copied in or out.  A long request runs alone through the device-wide sort with its reserved
+// range of the arena as its workspace.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -26,31 +28,31 @@ class HipExecutor : public srv::Executor {
   struct SlotRes {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    char* arena = nullptr;
+    char* header = nullptr;  // [control block][descriptor array] on the device
     SegDesc* h_desc = nullptr;
     SegCtl* ctl = nullptr;
     SegDesc* d_desc = nullptr;
-    char* scratch = nullptr;
   };
 
   ap_status init(int nslots, size_t budget, int max_batch) {
     if (hipGetDevice(&dev_) != hipSuccess) return fail(AP_ERR_HIP, "hipGetDevice failed");
     tile_ = 2048;  // smallest tile of any configuration: longer requests get scratch
     max_batch_ = max_batch;
-    header_ = up256s(sizeof(SegCtl)) + up256s(sizeof(SegDesc) * (size_t)max_batch);
-    const size_t arena = (budget / (size_t)nslots) / 256 * 256;
-    if (arena <= header_ + 256) return fail(AP_ERR_BUDGET, "budget too small for %d slots", nslots);
-    cap_ = arena - header_;
+    const size_t header = up256s(sizeof(SegCtl)) + up256s(sizeof(SegDesc) * (size_t)max_batch);
+    budget_ = budget / 256 * 256;
+    if (budget_ < layout_for(0).total) return fail(AP_ERR_BUDGET, "budget below the minimum of %zu bytes",
+                                                   layout_for(0).total);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&arena_), budget_);
+    if (e != hipSuccess) return hip_fail(e, "server scratch arena allocation");
     slots_.resize(nslots);
     for (auto& sl : slots_) {
-      hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+      e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.arena), arena);
+      if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sl.header), header);
       if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&sl.h_desc), sizeof(SegDesc) * max_batch);
       if (e != hipSuccess) return hip_fail(e, "server slot allocation");
-      sl.ctl = reinterpret_cast<SegCtl*>(sl.arena);
-      sl.d_desc = reinterpret_cast<SegDesc*>(sl.arena + up256s(sizeof(SegCtl)));
-      sl.scratch = sl.arena + header_;
+      sl.ctl = reinterpret_cast<SegCtl*>(sl.header);
+      sl.d_desc = reinterpret_cast<SegDesc*>(sl.header + up256s(sizeof(SegCtl)));
       ap_status st = fill_u32(reinterpret_cast<uint32_t*>(sl.ctl), 0u, up256s(sizeof(SegCtl)) / 4, sl.stream);
       if (st != AP_OK) return st;
     }
@@ -67,14 +69,15 @@ class HipExecutor : public srv::Executor {
     for (auto& sl : slots_) {
       if (sl.stream) (void)hipStreamSynchronize(sl.stream);
       if (sl.h_desc) (void)hipHostFree(sl.h_desc);
-      if (sl.arena) (void)hipFree(sl.arena);
+      if (sl.header) (void)hipFree(sl.header);
       if (sl.ev) (void)hipEventDestroy(sl.ev);
       if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
+    if (arena_) (void)hipFree(arena_);
   }
 
   int num_slots() const override { return (int)slots_.size(); }
-  size_t slot_capacity() const override { return cap_; }
+  size_t scratch_budget() const override { return budget_; }
 
   size_t scratch_bytes(const srv::Request& r, bool alone) const override {
     if (alone) return layout_for(r.n).total;
@@ -83,9 +86,10 @@ class HipExecutor : public srv::Executor {
 
   void thread_init() override { (void)hipSetDevice(dev_); }
 
-  ap_status launch_batch(int slot, std::vector<srv::Request*>& reqs) override {
+  ap_status launch_batch(int slot, std::vector<srv::Request*>& reqs, size_t scratch_off) override {
     ApRange range("ap_server batch");
     SlotRes& sl = slots_[slot];
+    char* const scratch = arena_ + scratch_off;
     std::sort(reqs.begin(), reqs.end(), [](const srv::Request* a, const srv::Request* b) { return a->n > b->n; });
     size_t used = 0;
     uint32_t cnt = 0;
@@ -95,7 +99,7 @@ class HipExecutor : public srv::Executor {
       d.dst = r->out;
       d.tmp = nullptr;
       if (r->n > tile_) {
-        d.tmp = reinterpret_cast<uint32_t*>(sl.scratch + used);
+        d.tmp = reinterpret_cast<uint32_t*>(scratch + used);
         used += up256s(r->n * sizeof(uint32_t));
       }
       d.spl = r->P > 1 ? r->spl : nullptr;
@@ -123,8 +127,7 @@ class HipExecutor : public srv::Executor {
         }
       }
       if (lo >= hi) continue;
-      launch_seg_cfg(grp[g].cfg, dim3(seg_workgroups(grp[g].cfg, hi - lo)), sl.stream, sl.d_desc, lo, hi, 0, 0, g,
-                     sl.ctl);
+      launch_seg_group(grp[g], dim3(seg_workgroups(grp[g], hi - lo)), sl.stream, sl.d_desc, lo, hi, g, sl.ctl);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_seg_sort");
@@ -132,15 +135,16 @@ class HipExecutor : public srv::Executor {
     return e == hipSuccess ? AP_OK : hip_fail(e, "hipEventRecord");
   }
 
-  ap_status launch_alone(int slot, srv::Request* r) override {
+  ap_status launch_alone(int slot, srv::Request* r, size_t scratch_off) override {
     SlotRes& sl = slots_[slot];
+    char* const scratch = arena_ + scratch_off;
     const Layout L = layout_for(r->n);
     ap_status st = AP_OK;
     if (r->n == 0) {
       if (r->P > 1 && r->spl) st = fill_u32(r->spl, 0xFFFFFFFFu, (size_t)r->P - 1, sl.stream);
     } else {
-      st = fill_u32(reinterpret_cast<uint32_t*>(sl.scratch), 0u, L.init_bytes / 4, sl.stream);
-      if (st == AP_OK) st = enqueue_sort(r->in, r->out, r->n, r->P, r->P > 1 ? r->spl : nullptr, sl.scratch, L,
+      st = fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, L.init_bytes / 4, sl.stream);
+      if (st == AP_OK) st = enqueue_sort(r->in, r->out, r->n, r->P, r->P > 1 ? r->spl : nullptr, scratch, L,
                                          sl.stream);
     }
     if (st != AP_OK) return st;
@@ -159,8 +163,8 @@ class HipExecutor : public srv::Executor {
   int dev_ = 0;
   size_t tile_ = 8192;
   int max_batch_ = 256;
-  size_t header_ = 0;
-  size_t cap_ = 0;
+  size_t budget_ = 0;
+  char* arena_ = nullptr;  // the scratch arena, budget_ bytes
   std::vector<SlotRes> slots_;
 };
 
@@ -172,6 +176,13 @@ struct ap_server {
 };
 
 using namespace aps;
+
+// Nearest-rank percentile of a sorted, non-empty sample.
+static double sorted_pct(const std::vector<double>& v, double p) {
+  const double r = std::ceil(p * (double)v.size());
+  const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::max(0.0, r - 1.0));
+  return v[i];
+}
 
 extern "C" {
 
@@ -243,18 +254,22 @@ ap_status ap_server_get_stats(ap_server* s, ap_server_stats* out, int reset_late
   std::vector<double>& v = st.latency_us;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
-    auto pct = [&](double p) {
-      const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::max(0.0, p * (double)v.size() - 1.0 + 0.999999));
-      return v[i];
-    };
     double sum = 0;
     for (double x : v) sum += x;
-    out->p50_us = pct(0.50);
-    out->p99_us = pct(0.99);
+    out->p50_us = sorted_pct(v, 0.50);
+    out->p99_us = sorted_pct(v, 0.99);
     out->mean_us = sum / (double)v.size();
     out->max_us = v.back();
     out->latency_samples = v.size();
   }
+  std::vector<double>& q = st.queue_us;
+  if (!q.empty()) {
+    std::sort(q.begin(), q.end());
+    out->queue_p50_us = sorted_pct(q, 0.50);
+    out->queue_p99_us = sorted_pct(q, 0.99);
+  }
+  out->scratch_budget_bytes = st.scratch_total;
+  out->scratch_peak_bytes = st.scratch_peak;
   if (reset_latencies) s->core->reset_latencies();
   return AP_OK;
 }

@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <random>
+#include <cstdint>
+#include <algorithm>
 #include <thread>
 #include <vector>
 
@@ -39,31 +41,51 @@ class MockExecutor : public Executor {
       if (s.th.joinable()) s.th.join();
   }
   int num_slots() const override { return (int)slots_.size(); }
-  size_t slot_capacity() const override { return cap_; }
+  size_t scratch_budget() const override { return cap_; }
   size_t scratch_bytes(const Request& r, bool alone) const override {
     return alone ? r.n * 8 + 1024 : (r.n > 64 ? r.n * 4 : 0);
   }
-  ap_status launch_batch(int slot, std::vector<Request*>& reqs) override { return start(slot, reqs); }
-  ap_status launch_alone(int slot, Request* r) override {
+  ap_status launch_batch(int slot, std::vector<Request*>& reqs, size_t off) override {
+    size_t bytes = 0;
+    for (Request* r : reqs) bytes += Ledger::round_up(scratch_bytes(*r, false));
+    return start(slot, reqs, off, bytes);
+  }
+  ap_status launch_alone(int slot, Request* r, size_t off) override {
     std::vector<Request*> v{r};
     alone_runs++;
-    return start(slot, v);
+    return start(slot, v, off, Ledger::round_up(scratch_bytes(*r, true)));
   }
   int query(int slot) override { return slots_[slot].done.load() ? 1 : 0; }
 
   std::atomic<int> running{0}, max_running{0}, batches{0}, alone_runs{0};
   std::atomic<int> max_batch_seen{0};
+  std::atomic<int> overlaps{0}, out_of_arena{0};  // scratch ranges of running work that collide
+  std::atomic<size_t> max_bytes_in_flight{0};
 
  private:
   struct S {
     std::atomic<int> done;
     std::thread th;
+    size_t off = 0, bytes = 0;
     S() : done(1) {}
     S(const S&) = delete;
   };
-  ap_status start(int slot, std::vector<Request*>& reqs) {
+  ap_status start(int slot, std::vector<Request*>& reqs, size_t off, size_t bytes) {
     S& s = slots_[slot];
     if (s.th.joinable()) s.th.join();
+    // the new range must lie in the arena and miss every range of work still running
+    if (off + bytes > cap_) out_of_arena++;
+    size_t in_flight = bytes;
+    for (int o = 0; o < (int)slots_.size(); ++o) {
+      if (o == slot || slots_[o].done.load()) continue;
+      const S& t = slots_[o];
+      in_flight += t.bytes;
+      if (bytes && t.bytes && off < t.off + t.bytes && t.off < off + bytes) overlaps++;
+    }
+    size_t mb = max_bytes_in_flight.load();
+    while (in_flight > mb && !max_bytes_in_flight.compare_exchange_weak(mb, in_flight)) {}
+    s.off = off;
+    s.bytes = bytes;
     s.done.store(0);
     batches++;
     int b = (int)reqs.size();
@@ -243,12 +265,130 @@ static void test_shutdown_cancels_queued() {
   delete srv;
 }
 
+// The ledger against a brute-force model: a map of 256-byte units, first fit = the lowest run of
+// free units that is long enough.
+static void test_ledger_against_bitmap() {
+  const size_t units = 64, A = Ledger::kAlign;
+  Ledger L(units * A + 100);  // the tail below one unit is not usable
+  CHECK(L.total() == units * A);
+  std::vector<int> owner(units, -1);
+  struct Res { size_t off, bytes; };
+  std::vector<Res> live;
+  std::mt19937 rng(11);
+  size_t off = 7;
+  CHECK(L.reserve(0, &off) && off == 0 && L.used() == 0);
+  CHECK(!L.reserve(units * A + 1, &off) && L.used() == 0);
+  for (int step = 0; step < 4000; ++step) {
+    if (live.empty() || rng() % 3 != 0) {
+      const size_t bytes = 1 + rng() % (12 * A);
+      const size_t k = (bytes + A - 1) / A;
+      size_t want = SIZE_MAX;  // brute-force first fit
+      for (size_t u = 0; u + k <= units && want == SIZE_MAX; ++u) {
+        bool ok = true;
+        for (size_t j = u; j < u + k && ok; ++j) ok = owner[j] < 0;
+        if (ok) want = u;
+      }
+      const bool got = L.reserve(bytes, &off);
+      CHECK(got == (want != SIZE_MAX));
+      if (got) {
+        CHECK(off == want * A);
+        for (size_t j = want; j < want + k; ++j) owner[j] = 1;
+        live.push_back({off, bytes});
+      }
+    } else {
+      const size_t i = rng() % live.size();
+      L.release(live[i].off, live[i].bytes);
+      for (size_t j = live[i].off / A; j < (live[i].off + live[i].bytes + A - 1) / A; ++j) owner[j] = -1;
+      live.erase(live.begin() + i);
+    }
+    size_t used = 0, run = 0, best = 0;
+    for (size_t u = 0; u < units; ++u) {
+      used += owner[u] >= 0;
+      run = owner[u] < 0 ? run + 1 : 0;
+      best = std::max(best, run);
+    }
+    CHECK(L.used() == used * A);
+    CHECK(L.largest_free() == best * A);
+    CHECK(L.consistent());
+    if (g_fail) return;
+  }
+  for (const Res& r : live) L.release(r.off, r.bytes);
+  CHECK(L.used() == 0 && L.largest_free() == L.total() && L.consistent());
+}
+
+// One shared arena: a long request may take most of the budget (more than an even share per
+// slot), running work never shares a byte range, and the ledger is whole again at the end.
+static void test_shared_budget() {
+  const size_t cap = 1 << 20;
+  MockExecutor ex(4, cap, 1500);
+  Config c;
+  c.max_batch = 8;
+  c.alone_min_keys = 20000;
+  Server srv(c, &ex);
+  std::mt19937 rng(7);
+  uint64_t t = 0;
+  std::vector<uint32_t> huge(140000), hout(140000);
+  CHECK(srv.submit(huge.data(), hout.data(), 140000, 1, nullptr, 0, &t) == AP_ERR_BUDGET);  // 1.12 MB > 1 MiB
+  const int N = 120;
+  std::vector<Buf> b(N);
+  std::vector<uint64_t> tk(N);
+  std::vector<size_t> n(N);
+  for (int i = 0; i < N; ++i) {
+    n[i] = (i == 0) ? 100000                        // 0.80 MB: more than a quarter of the budget
+         : (i % 10 == 0) ? 30000 + rng() % 30000   // 0.24-0.48 MB, alone
+         : (i % 3 == 0) ? 40 : 500 + rng() % 4000;  // no scratch / some scratch, batched
+    fill(b[i], n[i], 3, rng);
+    CHECK(srv.submit(b[i].in.data(), b[i].out.data(), n[i], 3, b[i].spl.data(), 0, &tk[i]) == AP_OK);
+  }
+  for (int i = 0; i < N; ++i) CHECK(srv.wait(tk[i], -1) == AP_OK);
+  for (int i = 0; i < N; ++i) CHECK(correct(b[i], 3));
+  CHECK(ex.overlaps.load() == 0);
+  CHECK(ex.out_of_arena.load() == 0);
+  CHECK(ex.max_bytes_in_flight.load() <= cap);
+  CHECK(ex.max_running.load() >= 2);
+  CHECK(srv.scratch_in_use() == 0);
+  CHECK(srv.ledger_consistent());
+  Stats s = srv.stats();
+  CHECK(s.scratch_total == cap && s.scratch_peak >= 800000 && s.scratch_peak <= cap);
+  CHECK(s.queue_us.size() == (size_t)N && s.latency_us.size() == (size_t)N);
+  for (size_t i = 0; i < s.queue_us.size(); ++i) CHECK(s.queue_us[i] >= 0 && s.queue_us[i] <= s.latency_us[i]);
+}
+
+// A long request at the head that must wait for scratch is not starved by a stream of short ones:
+// while it waits only requests without scratch run, and it starts once running work returns
+// enough of the arena.
+static void test_long_head_waits_for_scratch() {
+  const size_t cap = 1 << 20;
+  MockExecutor ex(3, cap, 3000);
+  Config c;
+  c.max_batch = 4;
+  c.alone_min_keys = 20000;
+  Server srv(c, &ex);
+  std::mt19937 rng(9);
+  std::vector<Buf> b(40);
+  std::vector<uint64_t> tk(40);
+  std::vector<size_t> n(40);
+  for (int i = 0; i < 40; ++i) {
+    n[i] = (i < 2) ? 70000 : (i % 2 ? 30 : 2000);  // two 0.56 MB requests cannot run together
+    fill(b[i], n[i], 2, rng);
+    CHECK(srv.submit(b[i].in.data(), b[i].out.data(), n[i], 2, b[i].spl.data(), 0, &tk[i]) == AP_OK);
+  }
+  for (int i = 0; i < 40; ++i) CHECK(srv.wait(tk[i], -1) == AP_OK);
+  for (int i = 0; i < 40; ++i) CHECK(correct(b[i], 2));
+  CHECK(ex.overlaps.load() == 0 && ex.out_of_arena.load() == 0);
+  CHECK(ex.max_bytes_in_flight.load() <= cap);
+  CHECK(srv.scratch_in_use() == 0 && srv.ledger_consistent());
+}
+
 int main() {
   test_many_requests_two_threads();
   test_budget_queue_and_invalid();
   test_injected_fault_isolated();
   test_continuous_batching();
   test_shutdown_cancels_queued();
+  test_ledger_against_bitmap();
+  test_shared_budget();
+  test_long_head_waits_for_scratch();
   std::printf(g_fail ? "FAILED\n" : "ALL PASSED\n");
   return g_fail;
 }

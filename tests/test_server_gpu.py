@@ -116,16 +116,23 @@ def test_admission_under_tiny_budget():
     torch = torch_cuda()
     pool = Pool(1 << 20)
     with binding.Server(hbm_budget_bytes=8 << 20, num_streams=2, max_batch=16, alone_min_keys=1 << 30) as srv:
-        big = pool.dev["a"][:1 << 20]
+        n_over = (1 << 21) + 64                      # 8 MiB + 256 B of scratch: more than the whole budget
+        big = torch.empty(n_over, dtype=torch.int32, device="cuda")
         out = torch.empty_like(big)
-        st, _ = srv.try_submit_ptr(big.data_ptr(), out.data_ptr(), 1 << 20, 1)  # 4 MiB scratch > 4 MiB slot
+        st, _ = srv.try_submit_ptr(big.data_ptr(), out.data_ptr(), n_over, 1)
         assert st == AP_ERR_BUDGET
-        reqs = _requests(pool, 40, 1 << 16, 1 << 19, seed=3)   # each fits, together they exceed the budget
+        # one request whose 4 MiB of scratch is half the budget (more than an even share of two slots)
+        # runs; then 40 that each fit and together exceed the budget
+        reqs = [inputs.Request(-1, 1 << 20, "a", 0, 0.0)] + _requests(pool, 40, 1 << 16, 1 << 19, seed=3)
         st, outs, spls = _run(srv, pool, reqs)
         assert all(s == AP_OK for s in st)
         for r, o, sp in zip(reqs, outs, spls):
             w, ws = _want(pool, r)
             assert np.array_equal(o, w) and np.array_equal(sp, ws)
+        stats = srv.stats()
+        assert stats["scratch_budget_bytes"] == 8 << 20
+        assert (4 << 20) <= stats["scratch_peak_bytes"] <= (8 << 20)
+        assert 0 <= stats["queue_p50_us"] <= stats["p50_us"]
 
 
 def test_injected_fault_fails_only_its_ticket():
