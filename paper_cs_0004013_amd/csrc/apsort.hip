@@ -126,8 +126,10 @@ ap_status check_lane_order(hipStream_t s) {
 // Tiles grow with n: larger tiles mean fewer tiles, so the look-back chain between tiles is
 // shorter relative to the time between tile starts, and a bucket's run in a tile is longer, so
 // the scatter writes longer contiguous pieces.  The largest tile (16 waves x 32 keys per lane,
-// 148 KiB of LDS, one workgroup per CU) is used from 2^25 keys on; small arrays use small tiles
-// so that the grid still covers every compute unit.
+// 148 KiB of LDS, one workgroup per CU) is used from 2^22 keys on, although below 2^23 keys its
+// 128-255 tiles leave CUs idle: a tile's phases are latency-bound, and fewer, larger tiles finish
+// a pass sooner.  The thresholds are the fastest shape by measured sort time at each power of
+// two from 2^15 to 2^25 keys.
 constexpr int kBits = 8;
 constexpr int kRadix = 1 << kBits;
 constexpr int kDigits = (32 + kBits - 1) / kBits;
@@ -140,9 +142,9 @@ struct PassShape {
 static const PassShape kShapes[] = {{4, 8}, {4, 16}, {8, 32}, {16, 32}};  // 2K, 4K, 16K, 32K keys
 
 static int shape_for(size_t n) {
-  if (n >= ((size_t)1 << 25)) return 3;
-  if (n >= ((size_t)1 << 22)) return 2;
-  if (n >= ((size_t)1 << 19)) return 1;
+  if (n >= ((size_t)1 << 22)) return 3;
+  if (n >= ((size_t)1 << 20)) return 2;
+  if (n >= ((size_t)1 << 18)) return 1;
   return 0;
 }
 // The mask rank needs extra LDS that the 32K-key tile cannot spare; it uses the 16K-key shape.

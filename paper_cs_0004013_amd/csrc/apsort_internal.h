@@ -51,9 +51,10 @@ struct SegCtl;
 struct SegGroup {
   int cls_lo, cls_hi, cfg;  // ceil(log2(length)) class range and kernel configuration
 };
-void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
-                    int cls_hi, int grp, SegCtl* ctl);
-int seg_workgroups(int cfg, uint32_t nwork);
+void launch_seg_group(const SegGroup& g, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi,
+                      int grp, SegCtl* ctl);
+int seg_workgroups(const SegGroup& g, uint32_t nwork);
+bool seg_group_one_tile(const SegGroup& g);
 int seg_tile_keys(int cfg);
 void seg_groups(SegGroup* out);  // kSegGroups entries
 ap_status seg_groups_check(const SegGroup* grp);  // the used groups partition classes 1..31

@@ -45,40 +45,60 @@ constexpr int seg_lcopies() {
 
 // The rank with lane-ordered LDS atomics only on a device that passed the lane-order check
 // (lane_order_ok(), also false while the mask rank is forced by ap_set_rank_mode(1)); the ballot
-// rank otherwise.
+// rank otherwise.  A group whose segments all fit one tile never runs the histogram sweep of
+// longer segments, so it is built with a single histogram copy: its workgroup then needs a
+// fraction of the LDS (19 instead of 63 KiB for 2048-key tiles), which leaves room on a CU for
+// the workgroups of the groups running beside it.
 template <int BITS, int WAVES, int IPT>
-static void launch_seg_sort(dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
-                            int cls_hi, int grp, SegCtl* ctl) {
+static void launch_seg_sort(bool one_tile, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi,
+                            int cls_lo, int cls_hi, int grp, SegCtl* ctl) {
+  constexpr int LC = seg_lcopies<BITS>();
+  if (one_tile) {
+    if (lane_order_ok())
+      hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, 1, SEG_RANK_ATOMIC>), grid, dim3(WAVES * 64), 0, s, order, lo,
+                         hi, cls_lo, cls_hi, grp, ctl);
+    else
+      hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, 1, SEG_RANK_BALLOT>), grid, dim3(WAVES * 64), 0, s, order, lo,
+                         hi, cls_lo, cls_hi, grp, ctl);
+    return;
+  }
   if (lane_order_ok())
-    hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, seg_lcopies<BITS>(), SEG_RANK_ATOMIC>), grid, dim3(WAVES * 64),
-                       0, s, order, lo, hi, cls_lo, cls_hi, grp, ctl);
+    hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, LC, SEG_RANK_ATOMIC>), grid, dim3(WAVES * 64), 0, s, order, lo, hi,
+                       cls_lo, cls_hi, grp, ctl);
   else
-    hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, seg_lcopies<BITS>(), SEG_RANK_BALLOT>), grid, dim3(WAVES * 64),
-                       0, s, order, lo, hi, cls_lo, cls_hi, grp, ctl);
+    hipLaunchKernelGGL((k_seg_sort<BITS, WAVES, IPT, LC, SEG_RANK_BALLOT>), grid, dim3(WAVES * 64), 0, s, order, lo, hi,
+                       cls_lo, cls_hi, grp, ctl);
 }
 
-// One persistent kernel of configuration cfg over work items [lo, hi) (or, with hi == ~0u, over
-// the device-built work order's length classes [cls_lo, cls_hi]), taking items from head[grp].
-void launch_seg_cfg(int cfg, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi, int cls_lo,
-                    int cls_hi, int grp, SegCtl* ctl) {
-  switch (cfg) {
-    case 1: launch_seg_sort<8, 16, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 2: launch_seg_sort<8, 4, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 3: launch_seg_sort<8, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 4: launch_seg_sort<4, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 5: launch_seg_sort<8, 8, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 6: launch_seg_sort<6, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 7: launch_seg_sort<10, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 8: launch_seg_sort<11, 4, 8>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 9: launch_seg_sort<11, 8, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 10: launch_seg_sort<8, 16, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    case 11: launch_seg_sort<8, 8, 32>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
-    default: launch_seg_sort<8, 8, 16>(grid, s, order, lo, hi, cls_lo, cls_hi, grp, ctl); break;
+// Every segment of the group fits one tile of its configuration: the longest length of class c
+// is 2^c keys.
+bool seg_group_one_tile(const SegGroup& g) {
+  return g.cls_hi <= 30 && ((size_t)1 << g.cls_hi) <= (size_t)seg_tile_keys(g.cfg);
+}
+
+// One persistent kernel of the group's configuration over work items [lo, hi) (or, with
+// hi == ~0u, over the device-built work order's length classes of the group), taking items from
+// head[grp].
+void launch_seg_group(const SegGroup& g, dim3 grid, hipStream_t s, const SegDesc* order, uint32_t lo, uint32_t hi,
+                      int grp, SegCtl* ctl) {
+  const bool ot = seg_group_one_tile(g);
+  const int a = g.cls_lo, b = g.cls_hi;
+  switch (g.cfg) {
+    case 1: launch_seg_sort<8, 16, 8>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 2: launch_seg_sort<8, 4, 16>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 3: launch_seg_sort<8, 4, 8>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 4: launch_seg_sort<4, 4, 8>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 5: launch_seg_sort<8, 8, 8>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 6: launch_seg_sort<6, 4, 8>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 7: launch_seg_sort<10, 4, 8>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 8: launch_seg_sort<11, 4, 8>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 9: launch_seg_sort<11, 8, 16>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 10: launch_seg_sort<8, 16, 16>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    case 11: launch_seg_sort<8, 8, 32>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
+    default: launch_seg_sort<8, 8, 16>(ot, grid, s, order, lo, hi, a, b, grp, ctl); break;
   }
 }
 
-// Resident workgroups per CU of each configuration (LDS and registers allow two workgroups of up
-// to 512 threads, one of 1024), times the CU count, capped by the work.
 // LDS of one workgroup of each configuration (the kernel's only shared object).
 template <int BITS, int WAVES, int IPT>
 constexpr size_t seg_lds() {
@@ -101,11 +121,17 @@ static size_t seg_cfg_lds(int cfg) {
   }
 }
 
-// Persistent grid: as many workgroups as fit on the device at once (by threads and by the 160 KiB
-// of LDS per CU), at most one per work item.
-int seg_workgroups(int cfg, uint32_t nwork) {
-  int per_cu = (kSegCfgs[cfg].waves * 64 >= 1024) ? 1 : (kSegCfgs[cfg].waves <= 4 ? 4 : 2);
-  per_cu = std::max(1, std::min(per_cu, (int)((size_t)160 * 1024 / seg_cfg_lds(cfg))));
+// Persistent grid: as many workgroups as fit on the device at once (by threads: two workgroups of
+// up to 512 threads per CU, one of 1024; and by the 160 KiB of LDS per CU of the build with every
+// histogram copy), at most one per work item.  One-tile groups keep this grid although their
+// build needs less LDS: a larger grid for them measured slower on the mixed batches (1-1.3%), as
+// their extra workgroups crowd the CUs that the longer segments' group runs on, while the smaller
+// LDS alone lets the groups' workgroups share CUs better (the bucketing sort's local sorts, 2^15
+// buckets of ~2K keys: 1.04 -> 0.99 ms per sort).
+int seg_workgroups(const SegGroup& g, uint32_t nwork) {
+  const int waves = kSegCfgs[g.cfg].waves;
+  int per_cu = waves * 64 >= 1024 ? 1 : (waves <= 4 ? 4 : 2);
+  per_cu = std::max(1, std::min(per_cu, (int)((size_t)160 * 1024 / seg_cfg_lds(g.cfg))));
   return (int)std::max<uint32_t>(1u, std::min<uint32_t>(nwork, (uint32_t)(per_cu * device_cus())));
 }
 
@@ -333,15 +359,15 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
   bool first = true;
   for (int g = 0; g < kSegGroups; ++g) {
     if (grp[g].cls_lo > grp[g].cls_hi) continue;
-    const dim3 grid(seg_workgroups(grp[g].cfg, (uint32_t)nseg));
+    const dim3 grid(seg_workgroups(grp[g], (uint32_t)nseg));
     if (first) {
-      launch_seg_cfg(grp[g].cfg, grid, s, order, 0u, ~0u, grp[g].cls_lo, grp[g].cls_hi, g, ctl);
+      launch_seg_group(grp[g], grid, s, order, 0u, ~0u, g, ctl);
       first = false;
       continue;
     }
     e = hipStreamWaitEvent(aux[g], ev_fork, 0);
     if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(fork)");
-    launch_seg_cfg(grp[g].cfg, grid, aux[g], order, 0u, ~0u, grp[g].cls_lo, grp[g].cls_hi, g, ctl);
+    launch_seg_group(grp[g], grid, aux[g], order, 0u, ~0u, g, ctl);
     e = hipEventRecord(ev_join[g], aux[g]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, ev_join[g], 0);
     if (e != hipSuccess) return hip_fail(e, "segmented sort: join");

@@ -78,43 +78,67 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint32_t* __restrict
 // (in place: src == dst == keys + offset, scratch at the same offset of tmp).  A segment of
 // long_min keys or more gets a LongSeg slot and a range of flat tiles of long_tile keys instead;
 // both come from one 64-bit counter, so flat tile ranges increase with the slot.
+// Slots of the work order are claimed once per wave and class: the lanes of a wave whose
+// segments share a class take consecutive slots from one atomic add of their count.  (With one
+// add per segment, tens of thousands of segments of one class, as the buckets of the bucketing
+// sort are, serialize on that class's counter: ~250 us for 32K segments.)
 __global__ __launch_bounds__(256) void k_seg_fill(const uint32_t* __restrict__ off, uint32_t nseg, uint32_t n_total,
                                                  uint32_t long_min, uint32_t long_tile, SegCtl* __restrict__ ctl,
                                                  uint32_t* keys, uint32_t* tmp, SegDesc* __restrict__ order,
                                                  LongSeg* __restrict__ longs, uint32_t* __restrict__ long_hist) {
   if (ctl->bad) return;  // invalid offsets: no work
-  for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < nseg; s += gridDim.x * 256) {
-    const uint32_t a = off[s], b = off[s + 1];
-    if (b < a || b > n_total) continue;
-    const uint32_t len = b - a;
-    if (len < 2) continue;
-    if (len >= long_min) {
-      const uint32_t nt = (len + long_tile - 1) / long_tile;
-      const unsigned long long got =
-          __hip_atomic_fetch_add(&ctl->long_cursor, (1ull << 32) | nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t slot = (uint32_t)(got >> 32);
-      LongSeg& ls = longs[slot];
-      ls.keys = keys + a;
-      ls.tmp = tmp + a;
-      ls.n = len;
-      ls.first_tile = (uint32_t)got;
-      ls.ntiles = nt;
-      // The slot's bucket counts start at zero: where they sit in the workspace depends on the
-      // call's sizes, so nothing a previous call left there can be trusted.
-      uint4* h = reinterpret_cast<uint4*>(long_hist + (size_t)slot * 1024);
-      for (int i = 0; i < 256; ++i) h[i] = make_uint4(0u, 0u, 0u, 0u);
-      continue;
+  const int lane = threadIdx.x & 63;
+  // the loop bound is uniform over the workgroup, so every lane of a wave takes part in the ballots
+  for (uint32_t s0 = blockIdx.x * 256; s0 < nseg; s0 += gridDim.x * 256) {
+    const uint32_t s = s0 + threadIdx.x;
+    int c = -1;  // class of this lane's short segment, -1 if none
+    uint32_t a = 0u, len = 0u;
+    if (s < nseg) {
+      a = off[s];
+      const uint32_t b = off[s + 1];
+      if (b >= a && b <= n_total && b - a >= 2u) {
+        len = b - a;
+        if (len >= long_min) {
+          const uint32_t nt = (len + long_tile - 1) / long_tile;
+          const unsigned long long got = __hip_atomic_fetch_add(&ctl->long_cursor, (1ull << 32) | nt,
+                                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint32_t slot = (uint32_t)(got >> 32);
+          LongSeg& ls = longs[slot];
+          ls.keys = keys + a;
+          ls.tmp = tmp + a;
+          ls.n = len;
+          ls.first_tile = (uint32_t)got;
+          ls.ntiles = nt;
+          // The slot's bucket counts start at zero: where they sit in the workspace depends on
+          // the call's sizes, so nothing a previous call left there can be trusted.
+          uint4* h = reinterpret_cast<uint4*>(long_hist + (size_t)slot * 1024);
+          for (int i = 0; i < 256; ++i) h[i] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+          c = seg_class(len);
+        }
+      }
     }
-    const int c = seg_class(len);
-    SegDesc dsc;
-    dsc.src = keys + a;
-    dsc.dst = keys + a;
-    dsc.tmp = tmp + a;
-    dsc.spl = nullptr;
-    dsc.n = len;
-    dsc.P = 1u;
-    dsc.pad[0] = dsc.pad[1] = 0u;
-    order[ctl->start[c] + add_agent(&ctl->cursor[c], 1u)] = dsc;
+    uint64_t todo = __builtin_amdgcn_ballot_w64(c >= 0);
+    while (todo) {
+      const int leader = __builtin_ctzll(todo);  // wave-uniform
+      const int cl = __builtin_amdgcn_readlane(c, leader);
+      const uint64_t same = __builtin_amdgcn_ballot_w64(c == cl);
+      uint32_t first = 0u;
+      if (lane == leader) first = ctl->start[cl] + add_agent(&ctl->cursor[cl], (uint32_t)__popcll(same));
+      first = (uint32_t)__builtin_amdgcn_readlane((int)first, leader);
+      if (c == cl) {
+        SegDesc dsc;
+        dsc.src = keys + a;
+        dsc.dst = keys + a;
+        dsc.tmp = tmp + a;
+        dsc.spl = nullptr;
+        dsc.n = len;
+        dsc.P = 1u;
+        dsc.pad[0] = dsc.pad[1] = 0u;
+        order[first + lanes_below(same)] = dsc;
+      }
+      todo &= ~same;
+    }
   }
 }
 
