@@ -534,6 +534,8 @@ def run_served(st: ServedTrace, srv, arr_s) -> dict:
     stt = srv.stats(reset_latencies=True)
     return {"gkeys_s": round(st.total_keys / wall / 1e9, 3), "p50_ms": round(stt["p50_us"] / 1e3, 4),
             "p99_ms": round(stt["p99_us"] / 1e3, 4), "latency_from": "arrival",
+            "queue_p50_ms": round(stt["queue_p50_us"] / 1e3, 4), "queue_p99_ms": round(stt["queue_p99_us"] / 1e3, 4),
+            "scratch_peak_gib": round(stt["scratch_peak_bytes"] / 2**30, 3),
             "submit_lag_mean_ms": round(float(lag.mean()) / 1e6, 4),
             "submit_lag_max_ms": round(float(lag.max()) / 1e6, 3),
             "batches": stt["batches"] - st0["batches"], "alone": stt["alone"] - st0["alone"],
@@ -542,8 +544,12 @@ def run_served(st: ServedTrace, srv, arr_s) -> dict:
 
 def run_plain(st: ServedTrace, arr_s, closed_loop: bool = False) -> dict:
     """One plain ap_sort_u32 per request, FIFO on one stream, launched at its arrival time (or
-    back to back); latency = completion event - arrival.  The same device checks run on the
-    stream after every BATCH requests."""
+    back to back).  Latency = completion - arrival on the host clock, as the server measures it:
+    the loop polls the requests' completion events in order while it waits for the next arrival
+    (and once after each launch), and stamps each completion when it sees it.  The latency from
+    GPU event times (completion event - a start event recorded at t0) is kept beside it; it reads
+    lower, since it starts the clock when the GPU processes the start event, not at t0.  The same
+    device checks run on the stream after every BATCH requests."""
     torch, np = st.torch, st.np
     lib = st.b.lib()
     B = st.BATCH
@@ -554,26 +560,44 @@ def run_plain(st: ServedTrace, arr_s, closed_loop: bool = False) -> dict:
     start = torch.cuda.Event(enable_timing=True)
     sid = s.cuda_stream
     src, out, spl, n = st.src, st.out, st.spl, st.n
+    done_ns = np.zeros(st.nreq, dtype=np.int64)
+    seen = 0  # completions stamped: [0, seen)
+
+    def poll(launched):
+        nonlocal seen
+        while seen < launched and evs[seen].query():
+            done_ns[seen] = time.monotonic_ns()
+            seen += 1
+
+    arr_ns = None if closed_loop else (np.asarray(arr_s, dtype=np.float64) * 1e9).astype(np.int64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t0_ns = time.monotonic_ns()
     start.record(s)
     for i in range(st.nreq):
         if not closed_loop:
-            a = float(arr_s[i])
-            while time.perf_counter() - t0 < a:
-                pass
+            a = t0_ns + int(arr_ns[i])
+            while time.monotonic_ns() < a:
+                poll(i)
         r = lib.ap_sort_u32(int(src[i]), int(out[i]), int(n[i]), 64, int(spl[i]), sid)
         if r:
             raise RuntimeError(st.b.last_error())
         evs[i].record(s)
+        if not closed_loop:
+            poll(i + 1)
         if (i + 1) % B == 0 or i + 1 == st.nreq:
             st.check_batch(i // B, acc, mism, s)
+    if not closed_loop:
+        while seen < st.nreq:
+            poll(st.nreq)
     s.synchronize()
     wall = time.perf_counter() - t0
     res = {"gkeys_s": round(st.total_keys / wall / 1e9, 3), "req_s": round(st.nreq / wall, 1)}
     if not closed_loop:
-        lat = [start.elapsed_time(evs[i]) - float(arr_s[i]) * 1e3 for i in range(st.nreq)]
-        res.update({"p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4)})
+        lat = (done_ns - t0_ns - arr_ns) / 1e6
+        lat_ev = [start.elapsed_time(evs[i]) - float(arr_s[i]) * 1e3 for i in range(st.nreq)]
+        res.update({"p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4), "latency_from": "arrival",
+                    "p50_ms_gpu_events": round(pct(lat_ev, 50), 4), "p99_ms_gpu_events": round(pct(lat_ev, 99), 4)})
     res.update(st.verdict(acc, mism))
     return res
 
@@ -679,6 +703,8 @@ def main() -> int:
                     help="served form: requests with at least this many keys run the device-wide sort alone")
     ap.add_argument("--profile-leg", choices=["segmented", "segmented-long", "msd", "latency", "merge"], default=None,
                     help="run only that leg (for rocprofv3) and print its result")
+    ap.add_argument("--msd-dists", default="a,e",
+                    help="distributions of the msd profile leg (three sorts of 2^26 keys each)")
     ap.add_argument("--phase-trace", action="store_true",
                     help="print per-phase tile durations of k_pass at 2^26 (ap_debug_pass trace mode) as markdown")
     ap.add_argument("--copy-calib", action="store_true",
@@ -720,16 +746,20 @@ def main() -> int:
         print(json.dumps(leg_segmented_long(binding, torch, np, inputs, spl, steps=3)), flush=True)
         return 0
     if args.profile_leg == "msd":
-        # the bucketing variant alone (three sorts of 2^26 keys each of (a) and (e)), for its counters
+        # the bucketing variant alone (three sorts of 2^26 keys per distribution), for its counters;
+        # each output checked on the device (no descent, same multiset hash as the input)
         spl = torch.empty(63, dtype=torch.int32, device="cuda")
         res = {}
-        for dist in ("a", "e"):
+        for dist in args.msd_dists.split(","):
             t_in = torch.from_numpy(inputs.keyset(dist, N_MAIN, seed=1).keys.view(np.int32)).to("cuda")
             out = torch.empty_like(t_in)
             for _ in range(3):
                 binding.ap_sort_u32_msd(t_in, out, 64, spl)
-            torch.cuda.synchronize()
-            res[dist] = bool(torch.equal(out, torch.sort(t_in)[0]))
+            acc = torch.zeros((2, 3), dtype=torch.int64, device="cuda")
+            binding.ap_check_u32(t_in, acc[0])
+            binding.ap_check_u32(out, acc[1])
+            a = acc.cpu().numpy()
+            res[dist] = bool(a[1, 0] == 0 and a[0, 1] == a[1, 1] and a[0, 2] == a[1, 2])
         print(json.dumps({"msd_sorted": res}), flush=True)
         return 0
     if args.profile_leg == "latency":

@@ -38,16 +38,27 @@ def kernel_times(d: str) -> list[tuple[str, int, float]]:
     return [(r[0], int(r[1]), float(r[2])) for r in rows]  # average is in microseconds
 
 
-def counter_per_dispatch(d: str, counter: str, kernel_substr: str) -> tuple[float, int]:
-    """Mean of the counter over the dispatches of kernels whose name contains kernel_substr.
-    rocprofv3 reports the value per dispatch (summed over the device's instances)."""
+def _match(name: str, kernel_substr: str, exclude: tuple[str, ...] = ()) -> bool:
+    return kernel_substr in name and not any(x in name for x in exclude)
+
+
+def counter_per_dispatch(d: str, counter: str, kernel_substr: str,
+                         exclude: tuple[str, ...] = ()) -> tuple[float, int]:
+    """Mean of the counter over the dispatches of kernels whose name contains kernel_substr (and
+    none of the `exclude` substrings).  rocprofv3 reports the value per dispatch (summed over the
+    device's instances)."""
     con = _db(d)
     rows = con.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
                        "where counter_name = ? group by dispatch_id", (counter,)).fetchall()
-    vals = [float(v) for name, _, v in rows if kernel_substr in name]
+    vals = [float(v) for name, _, v in rows if _match(name, kernel_substr, exclude)]
     if not vals:
         raise ValueError(f"no {counter} samples for {kernel_substr} in {d}")
     return sum(vals) / len(vals), len(vals)
+
+
+def kernel_total_us(d: str, kernel_substr: str, exclude: tuple[str, ...] = ()) -> float:
+    """Summed duration (us) of the dispatches of the kernels counter_per_dispatch selects."""
+    return sum(calls * avg for name, calls, avg in kernel_times(d) if _match(name, kernel_substr, exclude))
 
 
 def main() -> int:
@@ -62,13 +73,20 @@ def main() -> int:
     ap.add_argument("--out", required=True)
     ap.add_argument("--cmd", default="")
     ap.add_argument("--title", default="")
+    ap.add_argument("--exclude", default="",
+                    help="comma-separated name substrings of kernels to leave out of the selection")
+    ap.add_argument("--units", type=int, default=0,
+                    help="also report totals over all dispatches divided by this many units of work "
+                         "(e.g. sorts), for kernels launched a varying number of times per unit")
+    ap.add_argument("--unit-name", default="sort")
     ap.add_argument("--source", default=KERNEL_SRC,
                     help="kernel source file(s), comma-separated, whose joint hash is recorded")
     args = ap.parse_args()
 
     kt = kernel_times(args.trace)
-    f_k, nf = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel)
-    w_k, nw = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel)
+    excl = tuple(x for x in args.exclude.split(",") if x)
+    f_k, nf = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel, excl)
+    w_k, nw = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel, excl)
     f_c, _ = counter_per_dispatch(args.fetch_copy, "FETCH_SIZE", args.copy_kernel)
     w_c, _ = counter_per_dispatch(args.write_copy, "WRITE_SIZE", args.copy_kernel)
     f_scale = COPY_BYTES / (f_c * 1024.0)
@@ -77,7 +95,7 @@ def main() -> int:
     write_b = w_k * 1024.0 * w_scale
     srcs = [x for x in args.source.split(",") if x]
     sha = hashlib.sha256(b"".join(open(x, "rb").read() for x in srcs)).hexdigest()[:16]
-    dur = [t for t in kt if args.kernel in t[0]]
+    dur = [t for t in kt if _match(t[0], args.kernel, excl)]
     lines = [f"# {args.title or args.kernel} rocprofv3 summary", ""]
     if args.cmd:
         lines += ["Commands (run from the repository root on an MI355X):", "", "```", args.cmd.strip(), "```", ""]
@@ -85,11 +103,18 @@ def main() -> int:
               "| kernel | calls | mean us |", "|---|---|---|"]
     for name, calls, avg in kt:
         lines.append(f"| {name.split('(')[0]} | {calls} | {avg:.2f} |")
-    lines += ["", "## HBM traffic of the kernel (rocprofv3 --pmc, per dispatch)", "",
+    sel = f"`{args.kernel}`" + (f" except {', '.join('`' + x + '`' for x in excl)}" if excl else "")
+    lines += ["", f"## HBM traffic of the kernels named {sel} (rocprofv3 --pmc, per dispatch)", "",
               f"- FETCH_SIZE mean over {nf} dispatches: {f_k:.1f} KiB (x{f_scale:.3f} copy calibration)",
               f"- WRITE_SIZE mean over {nw} dispatches: {w_k:.1f} KiB (x{w_scale:.3f} copy calibration)",
               f"- copy calibration: 256 MiB copy reads FETCH_SIZE {f_c:.1f} KiB, WRITE_SIZE {w_c:.1f} KiB", "",
-              "Values read by bench.py:", "",
+              ]
+    if args.units > 0:
+        u = args.units
+        lines += [f"Per {args.unit_name} ({u} in the run; totals over all {nf} dispatches / {u}):", "",
+                  f"- kernel time: {kernel_total_us(args.trace, args.kernel, excl) / u:.2f} us",
+                  f"- HBM fetch: {fetch_b * nf / u / 1e6:.2f} MB, write: {write_b * nw / u / 1e6:.2f} MB", ""]
+    lines += ["Values read by bench.py:", "",
               f"kernel: {args.kernel}",
               f"mean_duration_us: {sum(t[2] * t[1] for t in dur) / max(sum(t[1] for t in dur), 1):.3f}",
               f"fetch_bytes_per_launch: {fetch_b:.0f}",
