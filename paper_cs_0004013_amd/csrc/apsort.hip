@@ -274,16 +274,24 @@ static void launch_pass_dbg(const PassDebugState& st, bool atomic_rank, dim3 gri
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl,
                        void* ws, const Layout& L, hipStream_t s, const uint32_t* d_vin, uint32_t* d_vout,
                        int first_digit) {
-  char* w = static_cast<char*>(ws);
-  uint32_t* hist = reinterpret_cast<uint32_t*>(w + L.hist);
-  uint32_t* base = reinterpret_cast<uint32_t*>(w + L.base);
-  uint32_t* plan = reinterpret_cast<uint32_t*>(w + L.plan);
-  uint32_t* done = reinterpret_cast<uint32_t*>(w + L.done);
-  uint32_t* tctr = reinterpret_cast<uint32_t*>(w + L.tctr);
-  uint32_t* status = reinterpret_cast<uint32_t*>(w + L.status);
-  uint32_t* tmp = reinterpret_cast<uint32_t*>(w + L.tmp);
+  return enqueue_sort_parts(d_in, d_out, n, P, d_spl, ws, static_cast<char*>(ws) + L.tctr, L, s, d_vin, d_vout,
+                            first_digit);
+}
+
+ap_status enqueue_sort_parts(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ctl,
+                             void* scratch, const Layout& L, hipStream_t s, const uint32_t* d_vin, uint32_t* d_vout,
+                             int first_digit) {
+  char* c = static_cast<char*>(ctl);
+  char* w = static_cast<char*>(scratch);  // holds the layout from L.tctr on
+  uint32_t* hist = reinterpret_cast<uint32_t*>(c + L.hist);
+  uint32_t* base = reinterpret_cast<uint32_t*>(c + L.base);
+  uint32_t* plan = reinterpret_cast<uint32_t*>(c + L.plan);
+  uint32_t* done = reinterpret_cast<uint32_t*>(c + L.done);
+  uint32_t* tctr = reinterpret_cast<uint32_t*>(w);
+  uint32_t* status = reinterpret_cast<uint32_t*>(w + (L.status - L.tctr));
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(w + (L.tmp - L.tctr));
   const bool pairs = d_vout != nullptr;
-  uint32_t* vtmp = pairs ? reinterpret_cast<uint32_t*>(w + L.vtmp) : nullptr;
+  uint32_t* vtmp = pairs ? reinterpret_cast<uint32_t*>(w + (L.vtmp - L.tctr)) : nullptr;
   const uint32_t nn = (uint32_t)n;
   const int cus = device_cus();
   const int inplace = (d_in == d_out) ? 1 : 0;

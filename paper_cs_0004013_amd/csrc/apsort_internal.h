@@ -66,6 +66,11 @@ void seg_reset(hipStream_t s, SegCtl* ctl);
 ap_status enqueue_sort(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ws,
                        const Layout& L, hipStream_t s, const uint32_t* d_vin = nullptr, uint32_t* d_vout = nullptr,
                        int first_digit = 0);
+// enqueue_sort with the workspace in two pieces: ctl holds the layout's [0, L.init_bytes) (zero
+// before the first call and left zero by every call), scratch holds [L.tctr, L.total).
+ap_status enqueue_sort_parts(const uint32_t* d_in, uint32_t* d_out, size_t n, int P, uint32_t* d_spl, void* ctl,
+                             void* scratch, const Layout& L, hipStream_t s, const uint32_t* d_vin = nullptr,
+                             uint32_t* d_vout = nullptr, int first_digit = 0);
 ap_status cached_workspace(size_t need, hipStream_t s, void** out);
 // Arrays of at most kSmallSortMax keys: sorted in one launch by one workgroup (apsort_seg.hip).
 constexpr uint32_t kSmallSortMax = 16384;

@@ -1,7 +1,8 @@
 // HIP executor and C entry points of the sort-request server (ap_server_*).
 //
 // Each slot owns a non-blocking stream, a completion event and a small header on the device (the
-// segmented-sort control block and the descriptor array).  Scratch comes from one arena of the
+// segmented-sort control block, the descriptor array, and the device-wide sort's control words,
+// which are zeroed once and left zero by every sort).  Scratch comes from one arena of the
 // memory budget, shared by the slots through the core's ledger.  A batch of short requests
 // becomes one launch of the persistent segmented kernel over host-built descriptors (longest
 // first), each descriptor pointing at the caller's input and output buffers directly, so no key is
@@ -28,20 +29,21 @@ class HipExecutor : public srv::Executor {
   struct SlotRes {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    char* header = nullptr;  // [control block][descriptor array] on the device
+    char* header = nullptr;  // [control block][descriptor array][sort control] on the device
     SegDesc* h_desc = nullptr;
     SegCtl* ctl = nullptr;
     SegDesc* d_desc = nullptr;
+    char* sort_ctl = nullptr;  // [0, init_bytes) of the device-wide sort's workspace layout
   };
 
   ap_status init(int nslots, size_t budget, int max_batch) {
     if (hipGetDevice(&dev_) != hipSuccess) return fail(AP_ERR_HIP, "hipGetDevice failed");
     tile_ = 2048;  // smallest tile of any configuration: longer requests get scratch
     max_batch_ = max_batch;
-    const size_t header = up256s(sizeof(SegCtl)) + up256s(sizeof(SegDesc) * (size_t)max_batch);
+    const size_t sort_ctl = up256s(layout_for(0).init_bytes);
+    const size_t header = up256s(sizeof(SegCtl)) + up256s(sizeof(SegDesc) * (size_t)max_batch) + sort_ctl;
     budget_ = budget / 256 * 256;
-    if (budget_ < layout_for(0).total) return fail(AP_ERR_BUDGET, "budget below the minimum of %zu bytes",
-                                                   layout_for(0).total);
+    if (budget_ < 256) return fail(AP_ERR_BUDGET, "budget below the minimum of 256 bytes");
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&arena_), budget_);
     if (e != hipSuccess) return hip_fail(e, "server scratch arena allocation");
     slots_.resize(nslots);
@@ -53,7 +55,9 @@ class HipExecutor : public srv::Executor {
       if (e != hipSuccess) return hip_fail(e, "server slot allocation");
       sl.ctl = reinterpret_cast<SegCtl*>(sl.header);
       sl.d_desc = reinterpret_cast<SegDesc*>(sl.header + up256s(sizeof(SegCtl)));
+      sl.sort_ctl = sl.header + (header - sort_ctl);
       ap_status st = fill_u32(reinterpret_cast<uint32_t*>(sl.ctl), 0u, up256s(sizeof(SegCtl)) / 4, sl.stream);
+      if (st == AP_OK) st = fill_u32(reinterpret_cast<uint32_t*>(sl.sort_ctl), 0u, sort_ctl / 4, sl.stream);
       if (st != AP_OK) return st;
     }
     ap_status st = check_lane_order(slots_[0].stream);
@@ -80,7 +84,10 @@ class HipExecutor : public srv::Executor {
   size_t scratch_budget() const override { return budget_; }
 
   size_t scratch_bytes(const srv::Request& r, bool alone) const override {
-    if (alone) return layout_for(r.n).total;
+    if (alone) {
+      const Layout L = layout_for(r.n);
+      return L.total - L.tctr;  // the control words live in the slot's header
+    }
     return r.n > tile_ ? up256s(r.n * sizeof(uint32_t)) : 0;  // one-tile requests need no scratch
   }
 
@@ -143,9 +150,8 @@ class HipExecutor : public srv::Executor {
     if (r->n == 0) {
       if (r->P > 1 && r->spl) st = fill_u32(r->spl, 0xFFFFFFFFu, (size_t)r->P - 1, sl.stream);
     } else {
-      st = fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, L.init_bytes / 4, sl.stream);
-      if (st == AP_OK) st = enqueue_sort(r->in, r->out, r->n, r->P, r->P > 1 ? r->spl : nullptr, scratch, L,
-                                         sl.stream);
+      st = enqueue_sort_parts(r->in, r->out, r->n, r->P, r->P > 1 ? r->spl : nullptr, sl.sort_ctl, scratch, L,
+                              sl.stream);
     }
     if (st != AP_OK) return st;
     hipError_t e = hipEventRecord(sl.ev, sl.stream);

@@ -219,6 +219,11 @@ class Server {
     pending_.push_back(r);
     stats_.submitted++;
     arrivals_++;
+    if (last_arrival_ns_) {  // running mean of the gaps between arrivals (weight 1/8)
+      const uint64_t gap = t_now > last_arrival_ns_ ? t_now - last_arrival_ns_ : 0;
+      gap_ewma_ns_ = gap_ewma_ns_ ? gap_ewma_ns_ - gap_ewma_ns_ / 8 + gap / 8 : gap;
+    }
+    last_arrival_ns_ = t_now;
     *ticket = r->ticket;
     cv_work_.notify_one();
     return AP_OK;
@@ -370,13 +375,20 @@ class Server {
     return true;
   }
 
+  // How long the loop polls without sleeping after an event: twice the mean gap between
+  // arrivals, so that at a steady rate the next request usually finds it awake, within
+  // [kSpinMinNs, kSpinMaxNs], so that a quiet server sleeps.
+  uint64_t spin_window_ns() const {
+    return std::min(kSpinMaxNs, std::max(kSpinMinNs, 2 * gap_ewma_ns_));
+  }
+
   void loop() {
-    // While device work is in flight, or for kSpinNs after the last launch, completion or arrival,
-    // the loop polls without sleeping (yielding the core between polls): waking a sleeping thread
-    // costs tens of microseconds, as much as a short request's device time.  After that it waits
-    // in steps of kPollUs while work is in flight, and blocks when there is none; the default
-    // 50 us timer slack of a Linux thread would stretch every such wait to ~70 us, so it is cut to
-    // 1 us.
+    // While device work is in flight, or for spin_window_ns() after the last launch, completion
+    // or arrival, the loop polls without sleeping (yielding the core between polls): waking a
+    // sleeping thread costs tens of microseconds, as much as a short request's device time.
+    // After that it waits in steps of kPollUs while work is in flight, and blocks when there is
+    // none; the default 50 us timer slack of a Linux thread would stretch every such wait to
+    // ~70 us, so it is cut to 1 us.
     (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     ex_->thread_init();
     std::vector<Request*> batch;
@@ -455,8 +467,9 @@ class Server {
         seen_arrivals = arrivals_;
         last_event = now_ns();
       }
+      const uint64_t spin = spin_window_ns();
       if (any_busy || !pending_.empty()) {
-        if (now_ns() - last_event < kSpinNs) {
+        if (now_ns() - last_event < spin) {
           lk.unlock();
           std::this_thread::yield();
           lk.lock();
@@ -464,7 +477,7 @@ class Server {
           // device work in flight: poll again shortly, or earlier if a request arrives
           cv_work_.wait_for(lk, std::chrono::microseconds(kPollUs));
         }
-      } else if (now_ns() - last_event < kSpinNs) {
+      } else if (now_ns() - last_event < spin) {
         lk.unlock();
         std::this_thread::yield();
         lk.lock();
@@ -488,8 +501,9 @@ class Server {
   bool joined_ = false;
   Ledger ledger_;
   uint64_t arrivals_ = 0;  // requests queued so far (the loop notes new ones to keep spinning)
-  static constexpr int kPollUs = 10;            // completion polling interval after the spin window
-  static constexpr uint64_t kSpinNs = 200000;   // poll without sleeping this long after any event
+  uint64_t last_arrival_ns_ = 0, gap_ewma_ns_ = 0;
+  static constexpr int kPollUs = 10;  // completion polling interval after the spin window
+  static constexpr uint64_t kSpinMinNs = 200000, kSpinMaxNs = 2000000;  // bounds of the spin window
   std::thread worker_;
 };
 
