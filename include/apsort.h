@@ -483,8 +483,8 @@ ap_status ap_debug_pass(int mode, uint64_t seed, unsigned long long *d_trace, si
 /*
  * Tile shape of the device-wide digit pass (Sec. 3.2 partial sort and
  * distribution, one digit of the LSD sort of Sec. 3.3.1).  By default the
- * tile grows with the array: 2K keys below 2^19, 4K below 2^22, 16K below
- * 2^25, 32K from there on (the mask rank uses 16K where 32K is chosen).
+ * tile grows with the array: 2K keys below 2^18, 4K below 2^20, 16K below
+ * 2^22, 32K from there on (the mask rank uses 16K where 32K is chosen).
  * shape: -1 = by size (default), 0..3 = always 2K, 4K, 16K, 32K keys.
  * Process-wide, for tests and tuning; results do not depend on it.  A
  * workspace sized by ap_sort_workspace_bytes before a change can be too small

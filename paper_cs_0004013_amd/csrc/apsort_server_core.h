@@ -1,5 +1,6 @@
 // Scheduling core of the sort-request server: tickets, a bounded arrival queue, admission under a
-// memory budget, continuous batching into per-slot launches, completion and latency statistics.
+// memory budget, continuous batching into launches on a few streams (slots), completion and
+// latency statistics.
 //
 // The core knows nothing about HIP: device work goes through the Executor interface (the HIP
 // executor lives in apsort_server.hip).  A slot is one stream; at most one batch (or one large
