@@ -134,7 +134,7 @@ constexpr int kBits = 8;
 constexpr int kRadix = 1 << kBits;
 constexpr int kDigits = (32 + kBits - 1) / kBits;
 constexpr int kHistThreads = 1024;  // one workgroup per CU (grid <= CUs)
-constexpr uint32_t kHistCopies = 32;  // copies of the global counters (contention / 32)
+constexpr uint32_t kHistCopies = kHistMaxCopies;  // copies of the global counters (contention / 32)
 
 struct PassShape {
   int waves, ipt;

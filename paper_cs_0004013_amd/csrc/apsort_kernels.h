@@ -48,6 +48,7 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t coun
 // Other widths use LCOPIES full-word copies, lane l using copy l % LCOPIES, HW+1 words apart.
 // ------------------------------------------------------------------------------------------------
 constexpr uint32_t kHistMaxVecPerThread = 1023;  // 4-key vectors counted by one thread, at most
+constexpr int kHistMaxCopies = 32;  // global copies of the counts (spreads the workgroups' atomic adds)
 template <int BITS, int THREADS, int LCOPIES>
 __global__ __launch_bounds__(THREADS) void k_hist_plan(
     const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restrict__ g_hist,
@@ -159,13 +160,16 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
   __syncthreads();
   const uint32_t used = gridDim.x < ncopies ? gridDim.x : ncopies;
   for (uint32_t j = tid; j < HW; j += THREADS) {
+    // every copy's count is loaded before any is summed: one round trip to memory, not one per
+    // group of copies (the loads cross the XCDs' caches)
     uint32_t c = 0u;
-    for (uint32_t cp0 = 0; cp0 < used; cp0 += 8) {
-      uint32_t part[8];
+    for (uint32_t cp0 = 0; cp0 < used; cp0 += kHistMaxCopies) {
+      uint32_t part[kHistMaxCopies];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) part[q] = (cp0 + q < used) ? ld_agent(&g_hist[(size_t)(cp0 + q) * HW + j]) : 0u;
+      for (int q = 0; q < kHistMaxCopies; ++q)
+        part[q] = (cp0 + q < used) ? ld_agent(&g_hist[(size_t)(cp0 + q) * HW + j]) : 0u;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) c += part[q];
+      for (int q = 0; q < kHistMaxCopies; ++q) c += part[q];
     }
     for (uint32_t cp = 0; cp < used; ++cp) g_hist[(size_t)cp * HW + j] = 0u;
     h[j] = c;
