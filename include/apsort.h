@@ -483,9 +483,12 @@ ap_status ap_debug_pass(int mode, uint64_t seed, unsigned long long *d_trace, si
 /*
  * Tile shape of the device-wide digit pass (Sec. 3.2 partial sort and
  * distribution, one digit of the LSD sort of Sec. 3.3.1).  By default the
- * tile grows with the array: 2K keys below 2^18, 4K below 2^20, 16K below
- * 2^22, 32K from there on (the mask rank uses 16K where 32K is chosen).
- * shape: -1 = by size (default), 0..3 = always 2K, 4K, 16K, 32K keys.
+ * tile (one workgroup of 16 waves) grows with the array: 4K keys below 2^17,
+ * 8K below 2^20, 16K below 2^22, 32K from there on (the mask rank uses 16K
+ * where 32K is chosen; key-value pairs use at most 8K below 2^22 and 16K from
+ * there on).
+ * shape: -1 = by size (default), 0..3 = always 4K, 8K, 16K, 32K keys (pairs:
+ * at most 16K).
  * Process-wide, for tests and tuning; results do not depend on it.  A
  * workspace sized by ap_sort_workspace_bytes before a change can be too small
  * afterwards (AP_ERR_INVALID).

@@ -123,13 +123,15 @@ ap_status check_lane_order(hipStream_t s) {
 
 // ---------------------------------------------------------------- configuration
 // Digit width and tile shapes of the single-array sort.  8-bit digits (4 passes for 32-bit keys).
-// Tiles grow with n: larger tiles mean fewer tiles, so the look-back chain between tiles is
-// shorter relative to the time between tile starts, and a bucket's run in a tile is longer, so
-// the scatter writes longer contiguous pieces.  The largest tile (16 waves x 32 keys per lane,
-// 148 KiB of LDS, one workgroup per CU) is used from 2^22 keys on, although below 2^23 keys its
-// 128-255 tiles leave CUs idle: a tile's phases are latency-bound, and fewer, larger tiles finish
-// a pass sooner.  The thresholds are the fastest shape by measured sort time at each power of
-// two from 2^15 to 2^25 keys.
+// Every tile is one workgroup of 16 waves; the tile grows with n (4, 8, 16 then 32 keys per
+// lane).  Larger tiles mean fewer tiles, so the look-back chain between tiles is shorter relative
+// to the time between tile starts, and a bucket's run in a tile is longer, so the scatter writes
+// longer contiguous pieces.  The largest tile (32 keys per lane, 148 KiB of LDS, one workgroup per
+// CU) is used from 2^22 keys on, although below 2^23 keys its 128-255 tiles leave CUs idle: a
+// tile's phases are latency-bound, and fewer, larger tiles finish a pass sooner.  Sixteen waves
+// split a tile's serial work (load, rank, reorder, scatter: one step per key of a lane) into
+// fewer steps than 4 or 8 waves holding the same tile.  Shapes and thresholds are the fastest by
+// measured sort time at every power of two and 1.5 times one from 2^15 to 1.5 * 2^25 keys.
 constexpr int kBits = 8;
 constexpr int kRadix = 1 << kBits;
 constexpr int kDigits = (32 + kBits - 1) / kBits;
@@ -139,12 +141,12 @@ constexpr uint32_t kHistCopies = kHistMaxCopies;  // copies of the global counte
 struct PassShape {
   int waves, ipt;
 };
-static const PassShape kShapes[] = {{4, 8}, {4, 16}, {8, 32}, {16, 32}};  // 2K, 4K, 16K, 32K keys
+static const PassShape kShapes[] = {{16, 4}, {16, 8}, {16, 16}, {16, 32}};  // 4K, 8K, 16K, 32K keys
 
 static int shape_for(size_t n) {
   if (n >= ((size_t)1 << 22)) return 3;
   if (n >= ((size_t)1 << 20)) return 2;
-  if (n >= ((size_t)1 << 18)) return 1;
+  if (n >= ((size_t)1 << 17)) return 1;
   return 0;
 }
 // The mask rank needs extra LDS that the 32K-key tile cannot spare; it uses the 16K-key shape.
@@ -182,8 +184,14 @@ static uint32_t hist_grid(size_t n, int cus) {
   return (uint32_t)std::max<size_t>(g, 1);
 }
 
-// Pairs (key + value) stage the values beside the keys in LDS, so their tile is at most 16K keys.
-static int shape_for_pairs(size_t n) { return std::min(shape_used(n, true), 2); }
+// Pairs (key + value) stage the values beside the keys in LDS, so their tile is at most 16K keys
+// (8 waves x 32 keys: with 16 waves the mask rank's words would not fit beside both stages), and
+// below 2^22 pairs the 8K-key tile measured faster than the 16K one.
+static int shape_for_pairs(size_t n) {
+  const int sh = shape_used(n, true);
+  if (g_shape_override.load() >= 0) return std::min(sh, 2);
+  return std::min(sh, n >= ((size_t)1 << 22) ? 2 : 1);
+}
 
 // Workspace layout (bytes from the 256-byte aligned base):
 //   [hist copies*D*R u32][base D*R u32][plan 32 u32][done 1 u32 | pad][tile counters 8 u32 | pad]
@@ -329,15 +337,15 @@ ap_status enqueue_sort_parts(const uint32_t* d_in, uint32_t* d_out, size_t n, in
     if (pairs) {
       switch (sh) {
         case 2: APS_PASS(8, 32, true); break;
-        case 1: APS_PASS(4, 16, true); break;
-        default: APS_PASS(4, 8, true); break;
+        case 1: APS_PASS(16, 8, true); break;
+        default: APS_PASS(16, 4, true); break;
       }
     } else {
       switch (sh) {
         case 3: APS_PASS(16, 32, false); break;
-        case 2: APS_PASS(8, 32, false); break;
-        case 1: APS_PASS(4, 16, false); break;
-        default: APS_PASS(4, 8, false); break;
+        case 2: APS_PASS(16, 16, false); break;
+        case 1: APS_PASS(16, 8, false); break;
+        default: APS_PASS(16, 4, false); break;
       }
     }
 #undef APS_PASS

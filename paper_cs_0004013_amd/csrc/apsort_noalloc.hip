@@ -18,7 +18,7 @@
 namespace aps {
 
 // Workspace of the largest accepted sort (AP_NOALLOC_MAX_KEYS keys): control block 133 KiB,
-// look-back status <= 8 MiB (4 passes x 2048 tiles of the smallest 2K-key shape x 256 buckets),
+// look-back status <= 4 MiB (4 passes x 1024 tiles of the smallest 4K-key shape x 256 buckets),
 // ping-pong buffer 16 MiB.  layout_for() is checked against this size on every call.
 constexpr size_t kNoAllocScratchBytes = (size_t)26 << 20;
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];

@@ -42,7 +42,9 @@ def _check(keys: np.ndarray, vals: np.ndarray | None = None, P: int = 64, inplac
     assert np.array_equal(gs, oracle.splitters(wk, P))
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 63, 2047, 2048, 2049, 70_001, (1 << 20) + 7, (1 << 22) + 77])
+# around the pairs' tile thresholds by size (2^17: 4K -> 8K keys; 2^22: 8K -> 16K keys)
+@pytest.mark.parametrize("n", [1, 2, 5, 63, 2047, 2048, 2049, 70_001, (1 << 17) - 1, 1 << 17, (1 << 20) + 7,
+                               (1 << 22) - 1, (1 << 22) + 77])
 def test_sizes(n):
     _check(inputs.keyset("e", n, seed=n % 97).keys)
 

@@ -36,8 +36,8 @@ def _exact(keys: np.ndarray, P: int = 64):
     assert np.array_equal(spl, oracle.splitters(want, P))
 
 
-# sizes across the four tile shapes by size (2K, 4K, 16K and 32K keys), each with a ragged last tile
-@pytest.mark.parametrize("n", [(1 << 17) + 77, (1 << 19) + 5, (1 << 21) + 3, (1 << 25) + 1001])
+# sizes across the four tile shapes by size (4K, 8K, 16K and 32K keys), each with a ragged last tile
+@pytest.mark.parametrize("n", [(1 << 16) + 77, (1 << 19) + 5, (1 << 21) + 3, (1 << 25) + 1001])
 @pytest.mark.parametrize("seed", [1, 2])
 def test_perturbed_uniform(debug_off, n, seed):
     torch_cuda()
@@ -76,7 +76,7 @@ def test_phase_trace(debug_off):
     b = debug_off
     n = (1 << 24) + 5
     keys = inputs.keyset("a", n, seed=4).keys
-    tile = 16 * 64 * 32 if n >= (1 << 22) else 8 * 64 * 32   # the shape chosen by size
+    tile = 16 * 64 * 32 if n >= (1 << 22) else 16 * 64 * 16   # the shape chosen by size
     ntiles = (n + tile - 1) // tile
     trace = torch.zeros((4 * ntiles + 16) * b.PASS_TRACE_WORDS, dtype=torch.int64, device="cuda")
     b.ap_debug_pass(2, 0, trace)

@@ -35,9 +35,9 @@ def test_uniform_2pow20_config():
     inv.check_splitters(out, 64, spl)
 
 
-# around the tile-shape thresholds by size (2^18, 2^20, 2^22) and the one-launch limit (16384)
+# around the tile-shape thresholds by size (2^17, 2^20, 2^22) and the one-launch limit (16384)
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 63, 64, 65, 255, 256, 257, 2047, 2048, 2049, 8191, 8192,
-                               8193, 16384, 16385, 100_000, (1 << 18) - 1, 1 << 18, (1 << 20) - 1, 1 << 20,
+                               8193, 16384, 16385, 100_000, (1 << 17) - 1, 1 << 17, (1 << 20) - 1, 1 << 20,
                                (1 << 20) + 7, (1 << 22) - 1, 1 << 22, (1 << 22) + 1, 3 * 8192 * 7 + 5])
 def test_sizes_full_range(n):
     rng = np.random.default_rng(n)
@@ -263,7 +263,7 @@ def test_match_rank_path(dist, n):
 @pytest.mark.parametrize("n", [70_001, (1 << 20) + 77])
 def test_pass_shapes(shape, n):
     """Every tile shape gives the oracle's result at sizes with a ragged last tile (by size, the
-    32K-key tile runs only from 2^22 keys on and the 2K-key tile only below 2^18)."""
+    32K-key tile runs only from 2^22 keys on and the 4K-key tile only below 2^17)."""
     from paper_cs_0004013_amd import binding
     binding.ap_set_pass_shape(shape)
     try:
