@@ -96,6 +96,15 @@ class HipExecutor : public srv::Executor {
   ap_status launch_batch(int slot, std::vector<srv::Request*>& reqs, size_t scratch_off) override {
     ApRange range("ap_server batch");
     SlotRes& sl = slots_[slot];
+    // A batch of one request short enough for one workgroup (what a lightly loaded server forms):
+    // the single-array sort's one launch, with no descriptor upload.
+    if (reqs.size() == 1 && reqs[0]->n >= 1 && reqs[0]->n <= kSmallSortMax) {
+      srv::Request* r = reqs[0];
+      const ap_status st = enqueue_small_sort(r->in, r->out, r->n, r->P, r->P > 1 ? r->spl : nullptr, sl.stream);
+      if (st != AP_OK) return st;
+      const hipError_t e = hipEventRecord(sl.ev, sl.stream);
+      return e == hipSuccess ? AP_OK : hip_fail(e, "hipEventRecord");
+    }
     char* const scratch = arena_ + scratch_off;
     std::sort(reqs.begin(), reqs.end(), [](const srv::Request* a, const srv::Request* b) { return a->n > b->n; });
     size_t used = 0;

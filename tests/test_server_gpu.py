@@ -177,6 +177,29 @@ def test_edge_requests_in_place_empty_tiny():
             assert np.array_equal(to_host(spl), oracle.splitters(w, 100))
 
 
+def test_lone_short_requests_one_launch():
+    """Requests submitted one at a time form batches of one; those of at most 16,384 keys take the
+    one-launch single-array sort, longer ones the segmented kernel.  Both match the oracle, in place
+    and out of place, at the tile edges of the one-launch shapes."""
+    from paper_cs_0004013_amd import binding
+    torch = torch_cuda()
+    rng = np.random.default_rng(21)
+    with binding.Server(hbm_budget_bytes=1 << 28, num_streams=2, alone_min_keys=1 << 16) as srv:
+        for n in (1, 2, 63, 2047, 2048, 2049, 8192, 8193, 16383, 16384, 16385, 40_000):
+            for inplace in (False, True):
+                announce(f"server lone request n={n} inplace={inplace}")
+                keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+                src = torch.from_numpy(keys.view(np.int32)).to("cuda")
+                out = src if inplace else torch.empty_like(src)
+                spl = torch.empty(63, dtype=torch.int32, device="cuda")
+                tk = srv.submit_ptr(src.data_ptr(), out.data_ptr(), n, 64, spl.data_ptr())
+                assert srv.wait(tk) == AP_OK
+                torch.cuda.synchronize()
+                w = oracle.sort_u32(keys)
+                assert np.array_equal(to_host(out), w)
+                assert np.array_equal(to_host(spl), oracle.splitters(w, 64))
+
+
 def test_destroy_cancels_queued():
     from paper_cs_0004013_amd import binding
     torch = torch_cuda()
