@@ -185,8 +185,9 @@ static uint32_t hist_grid(size_t n, int cus) {
 }
 
 // Pairs (key + value) stage the values beside the keys in LDS, so their tile is at most 16K keys
-// (8 waves x 32 keys: with 16 waves the mask rank's words would not fit beside both stages), and
-// below 2^22 pairs the 8K-key tile measured faster than the 16K one.
+// (16 waves x 16 keys with the atomic rank; 8 x 32 with the mask rank, whose words would not fit
+// beside both stages with 16 waves), and below 2^22 pairs the 8K-key tile measured faster than
+// the 16K one.
 static int shape_for_pairs(size_t n) {
   const int sh = shape_used(n, true);
   if (g_shape_override.load() >= 0) return std::min(sh, 2);
@@ -220,11 +221,13 @@ Layout layout_for(size_t n, bool pairs) {
   return L;
 }
 
-template <int W, int I, bool KV>
+// MATCH = false builds only the atomic-rank kernel (for shapes whose mask-rank words would not fit
+// the LDS); the caller then passes atomic_rank = true.
+template <int W, int I, bool KV, bool MATCH = true>
 static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out, uint32_t* tmp,
                         uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d, uint32_t* st_d,
                         uint32_t* tctr, const uint32_t* vin, uint32_t* vout, uint32_t* vtmp) {
-  if constexpr (W * 64 * I <= 16384) {
+  if constexpr (MATCH && W * 64 * I <= 16384) {
     if (!atomic_rank) {
       hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH, 4, KV>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d,
                          plan, base_d, st_d, tctr, vin, vout, vtmp);
@@ -336,7 +339,15 @@ ap_status enqueue_sort_parts(const uint32_t* d_in, uint32_t* d_out, size_t n, in
     launch_pass<W, I, KV>(atomic_rank, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr, d_vin, d_vout, vtmp)
     if (pairs) {
       switch (sh) {
-        case 2: APS_PASS(8, 32, true); break;
+        case 2:
+          // 16 waves when the atomic rank runs; the mask rank's words fit beside both stages only
+          // with 8 waves (same 16K-key tile)
+          if (atomic_rank)
+            launch_pass<16, 16, true, false>(true, grid, s, d_in, d_out, tmp, nn, d, plan, base_d, st_d, tctr, d_vin,
+                                             d_vout, vtmp);
+          else
+            APS_PASS(8, 32, true);
+          break;
         case 1: APS_PASS(16, 8, true); break;
         default: APS_PASS(16, 4, true); break;
       }
