@@ -90,12 +90,21 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """Open libapsort.so (raises if it has not been built)."""
+    """Open libapsort.so (raises if it has not been built).
+
+    PyTorch is imported first.  It bundles its own HIP runtime under the soname the library
+    links (libamdhip64.so.7), but asks for it by another name, so the dynamic loader shares one
+    runtime only when torch's copy is already loaded: opened the other way round, the process
+    would hold two HIP runtimes, and the second one to start finds no device."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_cs_0004013_amd.build` "
                                "(or __graft_entry__.build()) first")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(L, name)

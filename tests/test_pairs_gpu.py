@@ -124,6 +124,20 @@ def test_mask_rank_path():
         binding.ap_set_rank_mode(0)
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_mask_rank_every_tile_shape(shape):
+    """The mask rank on every pairs tile (its 16K tile is 8 waves x 32 keys, not the atomic rank's
+    16 x 16), with a ragged last tile and runs of equal keys."""
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_rank_mode(1)
+    binding.ap_set_pass_shape(shape)
+    try:
+        _check(inputs.keyset("d", 200_003 + shape, seed=40 + shape).keys)
+    finally:
+        binding.ap_set_pass_shape(-1)
+        binding.ap_set_rank_mode(0)
+
+
 def test_argsort_helper():
     torch = torch_cuda()
     from paper_cs_0004013_amd import binding

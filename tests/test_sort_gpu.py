@@ -247,9 +247,10 @@ def test_rank_self_check_passed():
 
 
 @pytest.mark.parametrize("dist", ["a", "d", "e"])
-@pytest.mark.parametrize("n", [12_345, (1 << 22) + 77])
+@pytest.mark.parametrize("n", [12_345, 70_001, (1 << 19) + 3, (1 << 21) + 9, (1 << 22) + 77])
 def test_match_rank_path(dist, n):
-    """The order-agnostic mask rank gives the same (oracle) result."""
+    """The order-agnostic mask rank gives the same (oracle) result: the one-launch path, and every
+    device-wide tile shape by size (4K, 8K and 16K keys; the 16K tile where 32K would be used)."""
     from paper_cs_0004013_amd import binding
     binding.ap_set_rank_mode(1)
     try:
