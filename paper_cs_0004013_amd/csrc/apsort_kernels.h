@@ -176,10 +176,30 @@ __global__ __launch_bounds__(THREADS) void k_hist_plan(
     if (out_hist) out_hist[j] = c;
     if (c == n) s_const[j / R] = 1u;  // one bucket holds every key: the digit is constant
   }
+  if constexpr (HW == THREADS && R % 64 == 0) {
+    // one counter per thread: every digit's exclusive scan at once (a wave scan, then the sums of
+    // the digit's earlier waves), two barriers instead of three per digit
+    __syncthreads();
+    const uint32_t lane = tid & 63u, wid = tid >> 6;
+    const uint32_t x0 = h[tid];
+    uint32_t x = x0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= (uint32_t)off) x += y;
+    }
+    if (lane == 63u) s_scan[wid] = x;
+    __syncthreads();
+    constexpr uint32_t WPD = R / 64;  // waves per digit
+    uint32_t pre = 0u;
+    for (uint32_t w = wid / WPD * WPD; w < wid; ++w) pre += s_scan[w];
+    g_base[tid] = pre + x - x0;
+  } else {
 #pragma unroll 1
-  for (int d = 0; d < D; ++d) {
-    lds_exclusive_scan<R, THREADS>(h + d * R, s_scan);
-    for (uint32_t j = tid; j < R; j += THREADS) g_base[d * R + j] = h[d * R + j];
+    for (int d = 0; d < D; ++d) {
+      lds_exclusive_scan<R, THREADS>(h + d * R, s_scan);
+      for (uint32_t j = tid; j < R; j += THREADS) g_base[d * R + j] = h[d * R + j];
+    }
   }
   if (tid == 0) {
     // Digits below first_digit are not sorted on here (the bucketing variant leaves them to the
