@@ -315,7 +315,7 @@ def test_small_arrays_one_launch(rank_mode):
         rng = np.random.default_rng(77)
         ws = torch.empty(binding.ap_sort_workspace_bytes(16384), dtype=torch.uint8, device="cuda")
         binding.ap_workspace_init(ws)
-        for n in (1, 2, 3, 100, 2047, 2048, 2049, 8191, 8192, 8193, 16383, 16384):
+        for n in (1, 2, 3, 100, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 16383, 16384):
             for dist in ("full", "e", "c"):
                 if dist == "full":
                     keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
