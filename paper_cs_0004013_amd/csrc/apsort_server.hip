@@ -93,7 +93,7 @@ class HipExecutor : public srv::Executor {
 
   void thread_init() override { (void)hipSetDevice(dev_); }
 
-  ap_status launch_batch(int slot, std::vector<srv::Request*>& reqs, size_t scratch_off) override {
+  ap_status launch_batch(int slot, std::vector<srv::Request*>& reqs, size_t scratch_off, size_t) override {
     ApRange range("ap_server batch");
     SlotRes& sl = slots_[slot];
     // A batch of one request short enough for one workgroup (what a lightly loaded server forms):
@@ -151,10 +151,14 @@ class HipExecutor : public srv::Executor {
     return e == hipSuccess ? AP_OK : hip_fail(e, "hipEventRecord");
   }
 
-  ap_status launch_alone(int slot, srv::Request* r, size_t scratch_off) override {
+  ap_status launch_alone(int slot, srv::Request* r, size_t scratch_off, size_t scratch_len) override {
     SlotRes& sl = slots_[slot];
     char* const scratch = arena_ + scratch_off;
     const Layout L = layout_for(r->n);
+    // The layout depends on the pass tile shape, a process-wide setting (ap_set_pass_shape): if it
+    // changed since the request was admitted, the reserved range may no longer hold the layout.
+    if (r->n && L.total - L.tctr > scratch_len)
+      return fail(AP_ERR_INVALID, "pass shape changed after the request was admitted: its scratch no longer fits");
     ap_status st = AP_OK;
     if (r->n == 0) {
       if (r->P > 1 && r->spl) st = fill_u32(r->spl, 0xFFFFFFFFu, (size_t)r->P - 1, sl.stream);

@@ -147,11 +147,11 @@ class Executor {
   virtual size_t scratch_bytes(const Request& r, bool alone) const = 0;
   // Size of the scratch arena that all slots share.
   virtual size_t scratch_budget() const = 0;
-  // Enqueue the batch on the slot, with scratch at [scratch_off, scratch_off + the batch's bytes)
-  // of the arena.  Returns AP_OK or an error (then every request of the batch
-  // fails with AP_ERR_DEVICE).
-  virtual ap_status launch_batch(int slot, std::vector<Request*>& reqs, size_t scratch_off) = 0;
-  virtual ap_status launch_alone(int slot, Request* r, size_t scratch_off) = 0;
+  // Enqueue the batch on the slot, with scratch at [scratch_off, scratch_off + scratch_len) of the
+  // arena (what scratch_bytes() asked for when the work was admitted).  Returns AP_OK or an error
+  // (then every request of the batch fails with AP_ERR_DEVICE).
+  virtual ap_status launch_batch(int slot, std::vector<Request*>& reqs, size_t scratch_off, size_t scratch_len) = 0;
+  virtual ap_status launch_alone(int slot, Request* r, size_t scratch_off, size_t scratch_len) = 0;
   // 1 = the slot's work completed, 0 = still running, < 0 = the device reported an error.
   virtual int query(int slot) = 0;
   virtual void thread_init() {}
@@ -443,7 +443,7 @@ class Server {
         }
         for (Request* r : batch) r->t_launch = t;
         lk.unlock();
-        const ap_status st = alone ? ex_->launch_alone(s, batch[0], off) : ex_->launch_batch(s, batch, off);
+        const ap_status st = alone ? ex_->launch_alone(s, batch[0], off, bytes) : ex_->launch_batch(s, batch, off, bytes);
         lk.lock();
         if (alone) stats_.alone++;
         else stats_.batches++;

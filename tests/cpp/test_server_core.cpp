@@ -45,21 +45,25 @@ class MockExecutor : public Executor {
   size_t scratch_bytes(const Request& r, bool alone) const override {
     return alone ? r.n * 8 + 1024 : (r.n > 64 ? r.n * 4 : 0);
   }
-  ap_status launch_batch(int slot, std::vector<Request*>& reqs, size_t off) override {
+  ap_status launch_batch(int slot, std::vector<Request*>& reqs, size_t off, size_t len) override {
     size_t bytes = 0;
     for (Request* r : reqs) bytes += Ledger::round_up(scratch_bytes(*r, false));
+    if (bytes > Ledger::round_up(len)) len_short++;
     return start(slot, reqs, off, bytes);
   }
-  ap_status launch_alone(int slot, Request* r, size_t off) override {
+  ap_status launch_alone(int slot, Request* r, size_t off, size_t len) override {
     std::vector<Request*> v{r};
     alone_runs++;
-    return start(slot, v, off, Ledger::round_up(scratch_bytes(*r, true)));
+    const size_t bytes = Ledger::round_up(scratch_bytes(*r, true));
+    if (bytes > Ledger::round_up(len)) len_short++;
+    return start(slot, v, off, bytes);
   }
   int query(int slot) override { return slots_[slot].done.load() ? 1 : 0; }
 
   std::atomic<int> running{0}, max_running{0}, batches{0}, alone_runs{0};
   std::atomic<int> max_batch_seen{0};
   std::atomic<int> overlaps{0}, out_of_arena{0};  // scratch ranges of running work that collide
+  std::atomic<int> len_short{0};                   // launches given less scratch than they need
   std::atomic<size_t> max_bytes_in_flight{0};
 
  private:
@@ -344,6 +348,7 @@ static void test_shared_budget() {
   for (int i = 0; i < N; ++i) CHECK(correct(b[i], 3));
   CHECK(ex.overlaps.load() == 0);
   CHECK(ex.out_of_arena.load() == 0);
+  CHECK(ex.len_short.load() == 0);
   CHECK(ex.max_bytes_in_flight.load() <= cap);
   CHECK(ex.max_running.load() >= 2);
   CHECK(srv.scratch_in_use() == 0);
