@@ -221,21 +221,44 @@ Layout layout_for(size_t n, bool pairs) {
   return L;
 }
 
+// Store hint of the keys-only scatter by array size.  Measured per sort of uniform keys: plain
+// stores are 7-13% faster from 2^23 to 3*2^24 keys (32-192 MiB, where a pass's output still sits
+// in the 256 MB last-level cache when the next pass reads it), and the non-temporal hint is faster
+// below (2^22: 0.086 vs 0.093 ms) and at 2^26 (0.62 vs 0.63 ms).
+static bool keys_store_nt(size_t n) { return n < ((size_t)1 << 23) || n > ((size_t)3 << 24); }
+
+template <int W, int I, bool KV, bool MATCH, bool NT>
+static void launch_pass_hint(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out,
+                             uint32_t* tmp, uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d,
+                             uint32_t* st_d, uint32_t* tctr, const uint32_t* vin, uint32_t* vout, uint32_t* vtmp) {
+  if constexpr (MATCH && W * 64 * I <= 16384) {
+    if (!atomic_rank) {
+      hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH, 4, KV, NT>), grid, dim3(W * 64), 0, s, in, out, tmp, n,
+                         d, plan, base_d, st_d, tctr, vin, vout, vtmp);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_ATOMIC, 4, KV, NT>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d,
+                     plan, base_d, st_d, tctr, vin, vout, vtmp);
+}
+
 // MATCH = false builds only the atomic-rank kernel (for shapes whose mask-rank words would not fit
-// the LDS); the caller then passes atomic_rank = true.
+// the LDS); the caller then passes atomic_rank = true.  Plain stores are built only for the
+// keys-only tiles of 16K keys and more, the shapes chosen at the sizes where they pay; a smaller
+// tile forced at those sizes keeps the hint.
 template <int W, int I, bool KV, bool MATCH = true>
 static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out, uint32_t* tmp,
                         uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d, uint32_t* st_d,
                         uint32_t* tctr, const uint32_t* vin, uint32_t* vout, uint32_t* vtmp) {
-  if constexpr (MATCH && W * 64 * I <= 16384) {
-    if (!atomic_rank) {
-      hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH, 4, KV>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d,
-                         plan, base_d, st_d, tctr, vin, vout, vtmp);
+  if constexpr (!KV && W * 64 * I >= 16384) {
+    if (!keys_store_nt(n)) {
+      launch_pass_hint<W, I, KV, MATCH, false>(atomic_rank, grid, s, in, out, tmp, n, d, plan, base_d, st_d, tctr,
+                                               vin, vout, vtmp);
       return;
     }
   }
-  hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_ATOMIC, 4, KV>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d, plan,
-                     base_d, st_d, tctr, vin, vout, vtmp);
+  launch_pass_hint<W, I, KV, MATCH, true>(atomic_rank, grid, s, in, out, tmp, n, d, plan, base_d, st_d, tctr, vin,
+                                          vout, vtmp);
 }
 
 // Debug mode of the digit pass (ap_debug_pass): the keys-only passes then run k_pass_dbg.

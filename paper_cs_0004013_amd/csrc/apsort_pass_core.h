@@ -107,7 +107,9 @@ __device__ __forceinline__ void dbg_stamp(const PassDebugArgs& dbg, uint32_t til
 // 30-bit count, zero before the pass).  The counters must have been cleared (pass_clear + barrier).
 // tid = threadIdx.x (a persistent caller passes it through an opaque copy, so that the addresses
 // derived from it are not hoisted out of its loop and kept in registers for every tile).
-template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV, int DBG = PASS_DBG_NONE>
+// NT_STORE (keys only): scatter with the non-temporal hint, else with plain stores.  A template
+// parameter: with a run-time flag the compiler merges the two stores into one plain store.
+template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV, int DBG = PASS_DBG_NONE, bool NT_STORE = true>
 __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK, KV>& sm, const uint32_t* __restrict__ src,
                                           uint32_t* __restrict__ dst, const uint32_t* __restrict__ vsrc,
                                           uint32_t* __restrict__ vdst, uint32_t n, uint32_t tile, int shift,
@@ -127,10 +129,11 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
   uint32_t k[IPT];
   uint32_t val[KV ? IPT : 1];
   const uint32_t wbase = tbase + (uint32_t)(wid * 64 * IPT + lane);
-  // Every key is read once and written once per pass, and a pass streams more bytes than the
-  // caches hold: for keys alone, loads and stores carry the non-temporal hint (3-7% faster per
-  // sort).  With values beside the keys (two streams each way) the hint made passes ~30% slower,
-  // so pairs use plain accesses.
+  // Every key is read once and written once per pass: for keys alone the loads carry the
+  // non-temporal hint (3-7% faster per sort), and so do the stores unless the caller asks for
+  // plain ones (NT_STORE false: arrays that fit the last-level cache, where the next pass reads
+  // back what this one wrote).  With values beside the keys (two streams each way) the hint made
+  // passes ~30% slower, so pairs use plain accesses.
   if (tbase + (uint32_t)T <= n) {
     if constexpr (KV) {
 #pragma unroll
@@ -274,8 +277,10 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
       if constexpr (KV) {
         gdst[sm.delta[v] + i] = key;
         gvdst[sm.delta[v] + i] = sm.vstage[i];
-      } else {
+      } else if constexpr (NT_STORE) {
         __builtin_nontemporal_store(key, &gdst[sm.delta[v] + i]);
+      } else {
+        gdst[sm.delta[v] + i] = key;
       }
     }
   }

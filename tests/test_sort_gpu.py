@@ -45,6 +45,21 @@ def test_sizes_full_range(n):
     _check(keys)
 
 
+# the keys-only scatter stores plainly from 2^23 to 3*2^24 keys and with the non-temporal hint
+# outside: both sides of both boundaries, with the atomic rank (32K tile) and the mask rank (16K)
+@pytest.mark.parametrize("rank_mode", [0, 1])
+@pytest.mark.parametrize("n", [(1 << 23) - 1, 1 << 23, 3 << 24, (3 << 24) + 1])
+def test_store_hint_boundaries(n, rank_mode):
+    from paper_cs_0004013_amd import binding
+    rng = np.random.default_rng(n + rank_mode)
+    keys = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    binding.ap_set_rank_mode(rank_mode)
+    try:
+        _check(keys)
+    finally:
+        binding.ap_set_rank_mode(0)
+
+
 @pytest.mark.parametrize("dist", inputs.DISTS)
 def test_distributions_2pow22(dist):
     _check(inputs.keyset(dist, (1 << 22) + 13, seed=11).keys)
