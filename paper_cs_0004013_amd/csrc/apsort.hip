@@ -227,25 +227,32 @@ Layout layout_for(size_t n, bool pairs) {
 // below (2^22: 0.086 vs 0.093 ms) and at 2^26 (0.62 vs 0.63 ms).
 static bool keys_store_nt(size_t n) { return n < ((size_t)1 << 23) || n > ((size_t)3 << 24); }
 
-template <int W, int I, bool KV, bool MATCH, bool NT>
+// Load hint of the pairs pass by array size.  Measured per pairs sort of uniform keys: loads with
+// the non-temporal hint are 6-11% faster from 2^24 to 2^25 pairs (128-256 MiB of keys and values,
+// where the dead input lines then leave the last-level cache to the output the next pass reads),
+// no faster at 2^22-3*2^22, and 1% slower at 3*2^24 and 2^26.
+static bool pairs_load_nt(size_t n) { return n >= ((size_t)1 << 24) && n <= ((size_t)1 << 25); }
+
+template <int W, int I, bool KV, bool MATCH, bool NT, bool NTL = false>
 static void launch_pass_hint(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out,
                              uint32_t* tmp, uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d,
                              uint32_t* st_d, uint32_t* tctr, const uint32_t* vin, uint32_t* vout, uint32_t* vtmp) {
   if constexpr (MATCH && W * 64 * I <= 16384) {
     if (!atomic_rank) {
-      hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH, 4, KV, NT>), grid, dim3(W * 64), 0, s, in, out, tmp, n,
-                         d, plan, base_d, st_d, tctr, vin, vout, vtmp);
+      hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_MATCH, 4, KV, NT, NTL>), grid, dim3(W * 64), 0, s, in, out, tmp,
+                         n, d, plan, base_d, st_d, tctr, vin, vout, vtmp);
       return;
     }
   }
-  hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_ATOMIC, 4, KV, NT>), grid, dim3(W * 64), 0, s, in, out, tmp, n, d,
-                     plan, base_d, st_d, tctr, vin, vout, vtmp);
+  hipLaunchKernelGGL((k_pass<kBits, W, I, RANK_ATOMIC, 4, KV, NT, NTL>), grid, dim3(W * 64), 0, s, in, out, tmp, n,
+                     d, plan, base_d, st_d, tctr, vin, vout, vtmp);
 }
 
 // MATCH = false builds only the atomic-rank kernel (for shapes whose mask-rank words would not fit
-// the LDS); the caller then passes atomic_rank = true.  Plain stores are built only for the
-// keys-only tiles of 16K keys and more, the shapes chosen at the sizes where they pay; a smaller
-// tile forced at those sizes keeps the hint.
+// the LDS); the caller then passes atomic_rank = true.  The size-dependent hints (plain stores for
+// keys, non-temporal loads for pairs) are built only for the tiles of 16K keys and more, the
+// shapes chosen at the sizes where they pay; a smaller tile forced at those sizes keeps the
+// default accesses.
 template <int W, int I, bool KV, bool MATCH = true>
 static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out, uint32_t* tmp,
                         uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d, uint32_t* st_d,
@@ -254,6 +261,13 @@ static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32
     if (!keys_store_nt(n)) {
       launch_pass_hint<W, I, KV, MATCH, false>(atomic_rank, grid, s, in, out, tmp, n, d, plan, base_d, st_d, tctr,
                                                vin, vout, vtmp);
+      return;
+    }
+  }
+  if constexpr (KV && W * 64 * I >= 16384) {
+    if (pairs_load_nt(n)) {
+      launch_pass_hint<W, I, KV, MATCH, true, true>(atomic_rank, grid, s, in, out, tmp, n, d, plan, base_d, st_d,
+                                                    tctr, vin, vout, vtmp);
       return;
     }
   }

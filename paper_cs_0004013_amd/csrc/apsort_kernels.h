@@ -264,8 +264,9 @@ __global__ __launch_bounds__(256) void k_lane_order_probe(uint32_t* __restrict__
 // claimed from an atomic counter while the LDS counters are cleared, so tiles start in id order
 // and the look-back of a tile only waits on tiles that are already running.
 // ------------------------------------------------------------------------------------------------
-// NT_STORE: keys-only scatter with the non-temporal hint, else plain stores (see pass_tile).
-template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN = 4, bool KV = false, bool NT_STORE = true>
+// NT_STORE, NT_LOAD_KV: cache hints of the keys-only scatter and of the pairs' loads (pass_tile).
+template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN = 4, bool KV = false, bool NT_STORE = true,
+          bool NT_LOAD_KV = false>
 __global__ __launch_bounds__(WAVES * 64) void k_pass(
     const uint32_t* in, uint32_t* out, uint32_t* tmp, uint32_t n, int d,
     const uint32_t* __restrict__ plan, const uint32_t* __restrict__ g_base,
@@ -284,8 +285,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_pass(
   if (threadIdx.x == 0) s_tile = add_agent(tile_ctr + d, 1u);
   pass_clear(sm);
   __syncthreads();
-  pass_tile<BITS, WAVES, IPT, RANK, LB_WIN, KV, PASS_DBG_NONE, NT_STORE>(sm, src, dst, vsrc, vdst, n, s_tile, d * BITS,
-                                                                        g_base, status, (int)threadIdx.x);
+  pass_tile<BITS, WAVES, IPT, RANK, LB_WIN, KV, PASS_DBG_NONE, NT_STORE, NT_LOAD_KV>(
+      sm, src, dst, vsrc, vdst, n, s_tile, d * BITS, g_base, status, (int)threadIdx.x);
 }
 
 // k_pass (keys only) with a debug mode of pass_tile (PassDebug): seeded timing perturbation, or

@@ -107,9 +107,11 @@ __device__ __forceinline__ void dbg_stamp(const PassDebugArgs& dbg, uint32_t til
 // 30-bit count, zero before the pass).  The counters must have been cleared (pass_clear + barrier).
 // tid = threadIdx.x (a persistent caller passes it through an opaque copy, so that the addresses
 // derived from it are not hoisted out of its loop and kept in registers for every tile).
-// NT_STORE (keys only): scatter with the non-temporal hint, else with plain stores.  A template
-// parameter: with a run-time flag the compiler merges the two stores into one plain store.
-template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV, int DBG = PASS_DBG_NONE, bool NT_STORE = true>
+// NT_STORE (keys only): scatter with the non-temporal hint, else with plain stores.  NT_LOAD_KV
+// (pairs only): full-tile loads of keys and values with the non-temporal hint.  Template
+// parameters: with a run-time flag the compiler merges the two accesses into one plain access.
+template <int BITS, int WAVES, int IPT, int RANK, int LB_WIN, bool KV, int DBG = PASS_DBG_NONE, bool NT_STORE = true,
+          bool NT_LOAD_KV = false>
 __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK, KV>& sm, const uint32_t* __restrict__ src,
                                           uint32_t* __restrict__ dst, const uint32_t* __restrict__ vsrc,
                                           uint32_t* __restrict__ vdst, uint32_t n, uint32_t tile, int shift,
@@ -132,10 +134,16 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
   // Every key is read once and written once per pass: for keys alone the loads carry the
   // non-temporal hint (3-7% faster per sort), and so do the stores unless the caller asks for
   // plain ones (NT_STORE false: arrays that fit the last-level cache, where the next pass reads
-  // back what this one wrote).  With values beside the keys (two streams each way) the hint made
-  // passes ~30% slower, so pairs use plain accesses.
+  // back what this one wrote).  With values beside the keys (two streams each way) the hint on
+  // stores made passes ~30% slower, so pairs store plainly, and load with the hint only where the
+  // caller asks (NT_LOAD_KV: arrays whose keys and values just fit the last-level cache).
   if (tbase + (uint32_t)T <= n) {
-    if constexpr (KV) {
+    if constexpr (KV && NT_LOAD_KV) {
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) k[j] = __builtin_nontemporal_load(&gsrc[wbase + j * 64]);
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) val[j] = __builtin_nontemporal_load(&gvsrc[wbase + j * 64]);
+    } else if constexpr (KV) {
 #pragma unroll
       for (int j = 0; j < IPT; ++j) k[j] = gsrc[wbase + j * 64];
 #pragma unroll

@@ -49,6 +49,19 @@ def test_sizes(n):
     _check(inputs.keyset("e", n, seed=n % 97).keys)
 
 
+# the pairs pass loads with the non-temporal hint from 2^24 to 2^25 pairs and plainly outside:
+# both sides of both boundaries, with the atomic rank (16 x 16 tile) and the mask rank (8 x 32)
+@pytest.mark.parametrize("rank_mode", [0, 1])
+@pytest.mark.parametrize("n", [(1 << 24) - 1, 1 << 24, 1 << 25, (1 << 25) + 1])
+def test_load_hint_boundaries(n, rank_mode):
+    from paper_cs_0004013_amd import binding
+    binding.ap_set_rank_mode(rank_mode)
+    try:
+        _check(inputs.keyset("d", n, seed=n % 89 + rank_mode).keys)
+    finally:
+        binding.ap_set_rank_mode(0)
+
+
 @pytest.mark.parametrize("dist", inputs.DISTS)
 def test_distributions_with_payload(dist):
     ks = inputs.keyset(dist, (1 << 21) + 333, seed=17)
