@@ -222,16 +222,16 @@ Layout layout_for(size_t n, bool pairs) {
 }
 
 // Store hint of the keys-only scatter by array size.  Measured per sort of uniform keys: plain
-// stores are 7-13% faster from 2^23 to 3*2^24 keys (32-192 MiB, where a pass's output still sits
-// in the 256 MB last-level cache when the next pass reads it), and the non-temporal hint is faster
-// below (2^22: 0.086 vs 0.093 ms) and at 2^26 (0.62 vs 0.63 ms).
-static bool keys_store_nt(size_t n) { return n < ((size_t)1 << 23) || n > ((size_t)3 << 24); }
+// stores are 7-13% faster from 2^23 to 7*2^23 keys and 3.5% at 15*2^22 (32-240 MiB, where a pass's
+// output still sits in the 256 MB last-level cache when the next pass reads it); the
+// non-temporal hint is faster below (2^22: 0.086 vs 0.093 ms) and at 2^26 (0.62 vs 0.63 ms).
+static bool keys_store_nt(size_t n) { return n < ((size_t)1 << 23) || n > ((size_t)15 << 22); }
 
 // Load hint of the pairs pass by array size.  Measured per pairs sort of uniform keys: loads with
-// the non-temporal hint are 6-11% faster from 2^24 to 2^25 pairs (128-256 MiB of keys and values,
-// where the dead input lines then leave the last-level cache to the output the next pass reads),
-// no faster at 2^22-3*2^22, and 1% slower at 3*2^24 and 2^26.
-static bool pairs_load_nt(size_t n) { return n >= ((size_t)1 << 24) && n <= ((size_t)1 << 25); }
+// the non-temporal hint are 6-11% faster from 2^24 to 2^25 pairs and 3-4% up to 5*2^23 (128-320
+// MiB of keys and values, where the dead input lines then leave the last-level cache to the
+// output the next pass reads), no faster at 2^22-3*2^22, and 1% slower at 3*2^24 and 2^26.
+static bool pairs_load_nt(size_t n) { return n >= ((size_t)1 << 24) && n <= ((size_t)5 << 23); }
 
 template <int W, int I, bool KV, bool MATCH, bool NT, bool NTL = false>
 static void launch_pass_hint(bool atomic_rank, dim3 grid, hipStream_t s, const uint32_t* in, uint32_t* out,

@@ -49,10 +49,10 @@ def test_sizes(n):
     _check(inputs.keyset("e", n, seed=n % 97).keys)
 
 
-# the pairs pass loads with the non-temporal hint from 2^24 to 2^25 pairs and plainly outside:
+# the pairs pass loads with the non-temporal hint from 2^24 to 5*2^23 pairs and plainly outside:
 # both sides of both boundaries, with the atomic rank (16 x 16 tile) and the mask rank (8 x 32)
 @pytest.mark.parametrize("rank_mode", [0, 1])
-@pytest.mark.parametrize("n", [(1 << 24) - 1, 1 << 24, 1 << 25, (1 << 25) + 1])
+@pytest.mark.parametrize("n", [(1 << 24) - 1, 1 << 24, 5 << 23, (5 << 23) + 1])
 def test_load_hint_boundaries(n, rank_mode):
     from paper_cs_0004013_amd import binding
     binding.ap_set_rank_mode(rank_mode)

@@ -45,10 +45,10 @@ def test_sizes_full_range(n):
     _check(keys)
 
 
-# the keys-only scatter stores plainly from 2^23 to 3*2^24 keys and with the non-temporal hint
+# the keys-only scatter stores plainly from 2^23 to 15*2^22 keys and with the non-temporal hint
 # outside: both sides of both boundaries, with the atomic rank (32K tile) and the mask rank (16K)
 @pytest.mark.parametrize("rank_mode", [0, 1])
-@pytest.mark.parametrize("n", [(1 << 23) - 1, 1 << 23, 3 << 24, (3 << 24) + 1])
+@pytest.mark.parametrize("n", [(1 << 23) - 1, 1 << 23, 15 << 22, (15 << 22) + 1])
 def test_store_hint_boundaries(n, rank_mode):
     from paper_cs_0004013_amd import binding
     rng = np.random.default_rng(n + rank_mode)
