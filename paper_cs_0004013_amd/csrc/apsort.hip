@@ -221,11 +221,14 @@ Layout layout_for(size_t n, bool pairs) {
   return L;
 }
 
-// Store hint of the keys-only scatter by array size.  Measured per sort of uniform keys: plain
-// stores are 7-13% faster from 2^23 to 7*2^23 keys and 3.5% at 15*2^22 (32-240 MiB, where a pass's
-// output still sits in the 256 MB last-level cache when the next pass reads it); the
-// non-temporal hint is faster below (2^22: 0.086 vs 0.093 ms) and at 2^26 (0.62 vs 0.63 ms).
-static bool keys_store_nt(size_t n) { return n < ((size_t)1 << 23) || n > ((size_t)15 << 22); }
+// Store hint of the keys-only scatter, by array size and pass.  From 2^23 keys on, the passes
+// before the last store plainly: the next pass finds much of its input still in the 256 MB
+// last-level cache, and run-boundary lines shared by two tiles merge there instead of reaching
+// HBM twice as partial lines.  The last pass keeps the non-temporal hint, so that a sort pays the
+// write-back of its own output instead of leaving dirty lines to the next kernel.  Measured per
+// sort of uniform keys against the hint on every pass: 0.593 vs 0.623 ms at 2^26, 2.357 vs 2.477
+// at 2^28, 0.590 vs 0.618 at 3*2^25; below 2^23 plain stores are slower (2^22: 0.092 vs 0.087).
+static bool keys_store_nt(size_t n, int d) { return n < ((size_t)1 << 23) || d == kDigits - 1; }
 
 // Load hint of the pairs pass by array size.  Measured per pairs sort of uniform keys: loads with
 // the non-temporal hint are 6-11% faster from 2^24 to 2^25 pairs and 3-4% up to 5*2^23 (128-320
@@ -258,7 +261,7 @@ static void launch_pass(bool atomic_rank, dim3 grid, hipStream_t s, const uint32
                         uint32_t n, int d, const uint32_t* plan, const uint32_t* base_d, uint32_t* st_d,
                         uint32_t* tctr, const uint32_t* vin, uint32_t* vout, uint32_t* vtmp) {
   if constexpr (!KV && W * 64 * I >= 16384) {
-    if (!keys_store_nt(n)) {
+    if (!keys_store_nt(n, d)) {
       launch_pass_hint<W, I, KV, MATCH, false>(atomic_rank, grid, s, in, out, tmp, n, d, plan, base_d, st_d, tctr,
                                                vin, vout, vtmp);
       return;

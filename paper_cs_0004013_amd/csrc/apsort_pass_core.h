@@ -133,8 +133,8 @@ __device__ __forceinline__ void pass_tile(const PassSmem<BITS, WAVES, IPT, RANK,
   const uint32_t wbase = tbase + (uint32_t)(wid * 64 * IPT + lane);
   // Every key is read once and written once per pass: for keys alone the loads carry the
   // non-temporal hint (3-7% faster per sort), and so do the stores unless the caller asks for
-  // plain ones (NT_STORE false: arrays that fit the last-level cache, where the next pass reads
-  // back what this one wrote).  With values beside the keys (two streams each way) the hint on
+  // plain ones (NT_STORE false: a pass whose output the next pass reads, on arrays large enough
+  // that the merged run-boundary lines and the cache hits of the next pass pay).  With values beside the keys (two streams each way) the hint on
   // stores made passes ~30% slower, so pairs store plainly, and load with the hint only where the
   // caller asks (NT_LOAD_KV: arrays whose keys and values just fit the last-level cache).
   if (tbase + (uint32_t)T <= n) {

@@ -387,17 +387,23 @@ ap_status enqueue_segmented(uint32_t* d_keys, size_t n_total, const uint32_t* d_
       hipLaunchKernelGGL((k_seg_long_hist<32768>), dim3(cus), dim3(1024), 0, ls, ctl, longs, lhist, lstatus,
                          L.status_pass_words);
       hipLaunchKernelGGL(k_seg_long_plan, dim3(gp), dim3(256), 0, ls, ctl, longs, lhist, lbase);
-      for (int d = 0; d < 4; ++d)
-        hipLaunchKernelGGL((k_seg_long_pass<16, 32, RANK_ATOMIC>), dim3(cus), dim3(1024), 0, ls, ctl, longs, lbase,
-                           lstatus + (size_t)d * L.status_pass_words, d);
+      // plain stores before the last pass, the non-temporal hint on it (long segments hold at least
+      // 2^20 keys each; the single-array sort does the same from 2^23 keys on)
+      for (int d = 0; d < 3; ++d)
+        hipLaunchKernelGGL((k_seg_long_pass<16, 32, RANK_ATOMIC, false>), dim3(cus), dim3(1024), 0, ls, ctl, longs,
+                           lbase, lstatus + (size_t)d * L.status_pass_words, d);
+      hipLaunchKernelGGL((k_seg_long_pass<16, 32, RANK_ATOMIC, true>), dim3(cus), dim3(1024), 0, ls, ctl, longs,
+                         lbase, lstatus + (size_t)3 * L.status_pass_words, 3);
       hipLaunchKernelGGL((k_seg_long_copy<32768>), dim3(gc), dim3(256), 0, ls, ctl, longs);
     } else {
       hipLaunchKernelGGL((k_seg_long_hist<16384>), dim3(cus), dim3(1024), 0, ls, ctl, longs, lhist, lstatus,
                          L.status_pass_words);
       hipLaunchKernelGGL(k_seg_long_plan, dim3(gp), dim3(256), 0, ls, ctl, longs, lhist, lbase);
-      for (int d = 0; d < 4; ++d)
-        hipLaunchKernelGGL((k_seg_long_pass<8, 32, RANK_MATCH>), dim3(cus), dim3(512), 0, ls, ctl, longs, lbase,
-                           lstatus + (size_t)d * L.status_pass_words, d);
+      for (int d = 0; d < 3; ++d)
+        hipLaunchKernelGGL((k_seg_long_pass<8, 32, RANK_MATCH, false>), dim3(cus), dim3(512), 0, ls, ctl, longs,
+                           lbase, lstatus + (size_t)d * L.status_pass_words, d);
+      hipLaunchKernelGGL((k_seg_long_pass<8, 32, RANK_MATCH, true>), dim3(cus), dim3(512), 0, ls, ctl, longs, lbase,
+                         lstatus + (size_t)3 * L.status_pass_words, 3);
       hipLaunchKernelGGL((k_seg_long_copy<16384>), dim3(gc), dim3(256), 0, ls, ctl, longs);
     }
     e = hipEventRecord(ev_join[kSegGroups], ls);

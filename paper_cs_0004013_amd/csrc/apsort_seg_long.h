@@ -158,8 +158,9 @@ __global__ __launch_bounds__(256) void k_seg_long_plan(const SegCtl* __restrict_
 // takes the next flat tile from the pass's counter until none is left, so tiles start in
 // increasing order and a look-back only waits on tiles already taken by running workgroups, which
 // each process one tile at a time.  A tile of a segment whose digit is constant is skipped (the
-// whole segment skips the pass, so no tile of it is looked back at).
-template <int WAVES, int IPT, int RANK>
+// whole segment skips the pass, so no tile of it is looked back at).  NT_STORE: the scatter's
+// store hint (plain for the passes before the last, as in the single-array sort of large arrays).
+template <int WAVES, int IPT, int RANK, bool NT_STORE>
 __global__ __launch_bounds__(WAVES * 64) void k_seg_long_pass(SegCtl* __restrict__ ctl, const LongSeg* __restrict__ longs,
                                                              const uint32_t* __restrict__ base,
                                                              uint32_t* __restrict__ status, int d) {
@@ -191,9 +192,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_seg_long_pass(SegCtl* __restrict
       // an opaque copy of the thread index: see pass_tile
       int tid = (int)threadIdx.x;
       asm volatile("" : "+v"(tid));
-      pass_tile<8, WAVES, IPT, RANK, 4, false>(sm, rd ? ls.tmp : ls.keys, rd ? ls.keys : ls.tmp, nullptr, nullptr,
-                                               ls.n, f - ls.first_tile, 8 * d, base + (size_t)slot * 1024 + d * 256,
-                                               status + (size_t)ls.first_tile * 256, tid);
+      pass_tile<8, WAVES, IPT, RANK, 4, false, PASS_DBG_NONE, NT_STORE>(
+          sm, rd ? ls.tmp : ls.keys, rd ? ls.keys : ls.tmp, nullptr, nullptr, ls.n, f - ls.first_tile, 8 * d,
+          base + (size_t)slot * 1024 + d * 256, status + (size_t)ls.first_tile * 256, tid);
     }
     __syncthreads();  // every thread is done with this tile's LDS before the next claim
   }

@@ -45,10 +45,11 @@ def test_sizes_full_range(n):
     _check(keys)
 
 
-# the keys-only scatter stores plainly from 2^23 to 15*2^22 keys and with the non-temporal hint
-# outside: both sides of both boundaries, with the atomic rank (32K tile) and the mask rank (16K)
+# from 2^23 keys on, the keys-only passes before the last store plainly and the last pass with the
+# non-temporal hint; below, every pass uses the hint: both sides of the boundary and a large ragged
+# size, with the atomic rank (32K tile) and the mask rank (16K)
 @pytest.mark.parametrize("rank_mode", [0, 1])
-@pytest.mark.parametrize("n", [(1 << 23) - 1, 1 << 23, 15 << 22, (15 << 22) + 1])
+@pytest.mark.parametrize("n", [(1 << 23) - 1, 1 << 23, (1 << 26) + 3])
 def test_store_hint_boundaries(n, rank_mode):
     from paper_cs_0004013_amd import binding
     rng = np.random.default_rng(n + rank_mode)
