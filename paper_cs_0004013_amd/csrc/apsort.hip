@@ -227,7 +227,7 @@ Layout layout_for(size_t n, bool pairs) {
 // HBM twice as partial lines.  The last pass keeps the non-temporal hint, so that a sort pays the
 // write-back of its own output instead of leaving dirty lines to the next kernel.  Measured per
 // sort of uniform keys against the hint on every pass: 0.593 vs 0.623 ms at 2^26, 2.357 vs 2.477
-// at 2^28, 0.590 vs 0.618 at 3*2^25; below 2^23 plain stores are slower (2^22: 0.092 vs 0.087).
+// at 2^28, 0.894 vs 0.978 at 3*2^25; below 2^23 plain stores are slower (2^22: 0.092 vs 0.087).
 static bool keys_store_nt(size_t n, int d) { return n < ((size_t)1 << 23) || d == kDigits - 1; }
 
 // Load hint of the pairs pass by array size.  Measured per pairs sort of uniform keys: loads with
